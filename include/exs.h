@@ -1,0 +1,230 @@
+/*
+ * exs.h -- C ABI of the MI355X docking hot path (libexs.so).
+ *
+ * The library docks flexible ligands into rigid, pre-computed pocket grids and
+ * keeps each ligand's best pose, the data-parallel core of the screening
+ * method of the paper (Sec. 3.1 "The dock and score algorithm"; Sec. 3.2 "The
+ * only information required to dock and score a ligand in the target binding
+ * site is their description" -- every ligand x pocket pair is independent).
+ *
+ * Calls return 0 (EXS_OK) or a negative status; no C++ exception crosses the
+ * ABI.  exs_last_error() gives a message for the calling thread's last
+ * failure.  Every call is thread-safe.  Pointers are plain host pointers
+ * unless a comment says "device".  The library owns every device buffer it
+ * allocates (pocket grids, uploaded ligand batches, job results) until the
+ * matching unload/release call.  A `stream` argument is a hipStream_t passed
+ * as void* (NULL = the null stream); work and copies of a job are ordered on
+ * the stream it was launched on.
+ */
+#ifndef EXS_H
+#define EXS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    EXS_OK = 0,
+    EXS_EINVAL = -1,    /* invalid argument or input; nothing was queued     */
+    EXS_ENOMEM = -2,    /* device or host allocation failed / over budget    */
+    EXS_EDEVICE = -3,   /* a HIP runtime call failed                         */
+    EXS_ENOTREADY = -4, /* job still running (only with wait = 0)            */
+    EXS_ENOENT = -5     /* unknown pocket, batch or job handle               */
+};
+
+/* ---- texel storage of a pocket grid ------------------------------------- */
+enum { EXS_F32 = 0, EXS_BF16 = 1, EXS_F16 = 2 };
+
+/* ---- search flags -------------------------------------------------------- */
+enum {
+    EXS_FLAG_PERSISTENT = 1, /* one persistent launch pulling ligand tiles from a queue */
+    EXS_FLAG_GRAPH = 2       /* capture the job's launches in a hipGraph and replay it   */
+};
+
+/* ---- limits -------------------------------------------------------------- */
+#define EXS_MAX_ATOMS 128     /* atoms per ligand                    */
+#define EXS_MAX_ROT 32        /* rotatable bonds per ligand          */
+#define EXS_MAX_CHANNELS 16   /* atom types (grid channels) per pocket */
+#define EXS_MAX_ORIENT 1024   /* initial orientations per ligand     */
+#define EXS_MAX_TOPK 32       /* poses rescored in FP64 per ligand   */
+
+/* Library version string (static storage). */
+const char* exs_version(void);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* exs_last_error(void);
+
+/*
+ * Load a pocket grid and keep it resident on the current device.
+ * The pocket is constant during a run and fetched once (Sec. 3.2: pocket data
+ * is fetched once per process and placed where the implementation likes).
+ *   values      [channels][nz][ny][nx] FP32 texels, x fastest; one channel per
+ *               ligand atom type.  Host pointer, or device pointer when
+ *               values_on_device = 1.  Copied; the caller keeps ownership.
+ *   nx, ny, nz  texels per axis, each >= 2.
+ *   spacing_A   texel spacing (A), > 0.  Texel (i,j,k) sits at
+ *               origin_A + spacing_A * (i,j,k); the pocket centre is the grid
+ *               centre, where each ligand's centroid is placed.
+ *   storage     EXS_F32, EXS_BF16 or EXS_F16: texels are stored in this type
+ *               (round to nearest even); interpolation and accumulation run in
+ *               FP32.  The FP32 master copy is always kept as well: it feeds
+ *               the FP64 rescoring of the top poses.
+ *   pocket_id_out  receives the handle.
+ * Errors: EXS_EINVAL (bad sizes, channels > EXS_MAX_CHANNELS, non-finite
+ * texels), EXS_ENOMEM, EXS_EDEVICE.
+ */
+int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channels,
+                         double spacing_A, const double origin_A[3], int storage,
+                         int values_on_device, void* stream, int32_t* pocket_id_out);
+
+/* Free a pocket's device grids.  Jobs still using it must be released first. */
+int exs_unload_pocket(int32_t pocket_id);
+
+/*
+ * A batch of ligands in CSR form (host pointers; every array is read during
+ * exs_upload_ligands and not kept).  A ligand is its atoms' positions and
+ * types and its bonds (Sec. 4.1: atom positions, types and bonds), plus the
+ * list of torsional (rotatable) bonds (Sec. 3.1).
+ *   atom_offset [L+1]  ligand l owns atoms atom_offset[l] .. atom_offset[l+1]-1
+ *   x, y, z     [A]    input conformation (A)
+ *   type        [A]    atom type = grid channel, < channels of its pocket
+ *   bond_offset [L+1], bond_ij [2*nb]   bonds as pairs of ligand-local indices
+ *   rot_offset  [L+1], rot_bond [R]     rotatable bonds, as indices into the
+ *                                       ligand's own bond list, in search order
+ *   pocket_id   [L]    pocket handle each ligand is docked against
+ * A rotatable bond must be a bridge of the bond graph (not in a ring) with
+ * atom 0 on one side; the side without atom 0 turns.
+ */
+typedef struct {
+    int32_t n_ligands;
+    const int32_t* atom_offset;
+    const float* x;
+    const float* y;
+    const float* z;
+    const uint8_t* type;
+    const int32_t* bond_offset;
+    const int32_t* bond_ij;
+    const int32_t* rot_offset;
+    const int32_t* rot_bond;
+    const int32_t* pocket_id;
+} exs_ligand_batch;
+
+/*
+ * Validate a ligand batch, pack its topology (bond-distance exclusion masks,
+ * moving-atom masks of every rotatable bond, per-ligand cost) and upload it to
+ * the device on `stream`.  All-or-nothing: any invalid ligand gives EXS_EINVAL
+ * naming the ligand, and nothing is uploaded.  Invalid: n < 1 or
+ * n > EXS_MAX_ATOMS, more than EXS_MAX_ROT rotatable bonds, an atom type not
+ * below its pocket's channel count, a bond or rotatable-bond index out of
+ * range, a rotatable bond in a ring or not connected to atom 0, an unknown
+ * pocket.  batch_out receives the handle.
+ */
+int exs_upload_ligands(const exs_ligand_batch* batch, void* stream, int64_t* batch_out);
+
+/* Free an uploaded batch (jobs using it must be released first). */
+int exs_release_ligands(int64_t batch);
+
+/*
+ * Host-only view of how the library reads one ligand (no device call): the
+ * same validation as exs_upload_ligands (with `channels` standing for the
+ * pocket's channel count) and the packed topology it uploads.  Outputs (any
+ * may be NULL):
+ *   excl   [4*n]      exclusion row of atom i as 4 x uint32: bit j%32 of word
+ *                     j/32 set = pair (i, j) is left out of the clash term
+ *                     (bond distance <= 3, i.e. 1-2, 1-3, 1-4 pairs, or i == j)
+ *   rot_uv [2*nrot]   u, v of each rotatable bond, u on atom 0's side
+ *   moving [4*nrot]   atoms that turn with the bond (v's side, v excluded)
+ */
+int exs_pack_topology(int n, const float* x, const float* y, const float* z, const uint8_t* type,
+                      int channels, int nb, const int32_t* bond_ij, int nrot,
+                      const int32_t* rot_bond, uint32_t* excl, int32_t* rot_uv, uint32_t* moving);
+
+/*
+ * Search settings (Sec. 3.1: greedy optimisation with restarts; the paper
+ * uses 256 initial poses per ligand).
+ *   n_orient       K initial orientations (Fibonacci sphere), 1..EXS_MAX_ORIENT
+ *   torsion_steps  S: each rotatable bond tries the S-1 turns 2*pi*s/S;
+ *                  one of 8, 16, 32
+ *   passes         P optimisation passes (all bonds, then the rigid offsets)
+ *   n_offsets      1 (no rigid offsets) or 27 (offset_step_A * {-1,0,1}^3)
+ *   clash_cutoff_A, clash_penalty   penalty per non-1-2/1-3/1-4 atom pair
+ *                  closer than the cutoff
+ *   top_k          0, or 1..EXS_MAX_TOPK: rescore each ligand's top_k poses in
+ *                  FP64 from the FP32 master grid and pick the best by FP64
+ *   poses_per_lane 0 = auto, or 1, 2, 4 (orientations searched by one lane)
+ *   ligands_per_wg 0 = auto, or 1, 2, 4, 8 (ligands per workgroup)
+ *   flags          EXS_FLAG_* bits
+ */
+typedef struct {
+    int32_t n_orient;
+    int32_t torsion_steps;
+    int32_t passes;
+    int32_t n_offsets;
+    float offset_step_A;
+    float clash_cutoff_A;
+    float clash_penalty;
+    int32_t top_k;
+    int32_t poses_per_lane;
+    int32_t ligands_per_wg;
+    int32_t flags;
+} exs_search_params;
+
+/*
+ * A pose descriptor: the pose it names is
+ *   X = c + offset_step * tau + R_orient * FK_theta(X0 - mean(X0))
+ * where c is the pocket centre, R_orient the orientation's rotation and
+ * FK_theta turns each rotatable bond's moving side by theta[b] * 2*pi/S.
+ * Poses are deterministic, so a descriptor regenerates its pose (Sec. 3.1).
+ */
+typedef struct {
+    float score;        /* FP32 search score (lower is better)             */
+    float pad0;
+    double score_fp64;  /* FP64 rescoring score, or NaN when top_k = 0      */
+    int32_t orient;     /* orientation index k                              */
+    int8_t tau[3];      /* accumulated rigid offsets, units of offset_step  */
+    uint8_t n_rot;      /* rotatable bonds of the ligand                    */
+    uint8_t theta[EXS_MAX_ROT]; /* torsion of each rotatable bond, units 2*pi/S */
+} exs_pose_desc;
+
+/*
+ * Dock every ligand of an uploaded batch against its pocket, asynchronously
+ * on `stream`.  One launch per pocket (default), or one persistent launch
+ * over all pockets (EXS_FLAG_PERSISTENT).  job_out receives the handle.
+ * Errors: EXS_EINVAL (settings), EXS_ENOENT (unknown batch or a pocket
+ * unloaded since upload), EXS_ENOMEM, EXS_EDEVICE.
+ */
+int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
+                   int64_t* job_out);
+
+/*
+ * Best pose of every ligand of a job (the ligand's score is the score of its
+ * best pose, Sec. 3.1).  wait = 1 blocks until the job is done; wait = 0
+ * returns EXS_ENOTREADY while it runs.  Outputs (host, any may be NULL):
+ *   best_score [L]          FP32 score of the best pose (FP64 value when top_k > 0,
+ *                           rounded to float)
+ *   desc       [L]          descriptor of the best pose
+ *   coords     [A*3]        best-pose coordinates, atom-major x,y,z
+ *   topk       [L*top_k]    the top_k poses by FP32 score, ascending (top_k > 0)
+ */
+int exs_get_best_poses(int64_t job, int wait, float* best_score, exs_pose_desc* desc,
+                       float* coords, exs_pose_desc* topk);
+
+/*
+ * Final score and descriptor of every orientation of every ligand:
+ * score [L*K], desc [L*K] (host, either may be NULL).  Waits for the job.
+ */
+int exs_get_orientation_results(int64_t job, float* score, exs_pose_desc* desc);
+
+/* Device time of the job's kernels in ms (waits for the job). */
+int exs_job_elapsed_ms(int64_t job, float* ms);
+
+/* Free a job's device results. */
+int exs_release_job(int64_t job);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXS_H */

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of libexs.so: argument marshalling only.
+
+Every function has the name of the C entry point it calls (include/exs.h) and
+raises ``ExsError`` on a negative status.  Nothing here computes any part of
+the docking search: without the built library the import of ``lib()`` fails
+loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexs.so")
+
+EXS_OK, EXS_EINVAL, EXS_ENOMEM, EXS_EDEVICE, EXS_ENOTREADY, EXS_ENOENT = 0, -1, -2, -3, -4, -5
+EXS_F32, EXS_BF16, EXS_F16 = 0, 1, 2
+EXS_FLAG_PERSISTENT, EXS_FLAG_GRAPH = 1, 2
+EXS_MAX_ATOMS, EXS_MAX_ROT, EXS_MAX_CHANNELS, EXS_MAX_ORIENT, EXS_MAX_TOPK = 128, 32, 16, 1024, 32
+
+STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
+
+# exported symbols (kept in step with include/exs.h)
+SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
+           "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
+           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job")
+
+
+class ExsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("exs error %d: %s" % (code, msg))
+        self.code = code
+
+
+class exs_ligand_batch(C.Structure):
+    _fields_ = [("n_ligands", C.c_int32), ("atom_offset", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("z", C.c_void_p), ("type", C.c_void_p),
+                ("bond_offset", C.c_void_p), ("bond_ij", C.c_void_p), ("rot_offset", C.c_void_p),
+                ("rot_bond", C.c_void_p), ("pocket_id", C.c_void_p)]
+
+
+class exs_search_params(C.Structure):
+    _fields_ = [("n_orient", C.c_int32), ("torsion_steps", C.c_int32), ("passes", C.c_int32),
+                ("n_offsets", C.c_int32), ("offset_step_A", C.c_float),
+                ("clash_cutoff_A", C.c_float), ("clash_penalty", C.c_float),
+                ("top_k", C.c_int32), ("poses_per_lane", C.c_int32),
+                ("ligands_per_wg", C.c_int32), ("flags", C.c_int32)]
+
+
+# numpy view of exs_pose_desc (56 bytes, natural alignment)
+POSE_DESC = np.dtype([("score", "<f4"), ("pad0", "<f4"), ("score_fp64", "<f8"),
+                      ("orient", "<i4"), ("tau", "i1", (3,)), ("n_rot", "u1"),
+                      ("theta", "u1", (EXS_MAX_ROT,))])
+assert POSE_DESC.itemsize == 56
+
+_lib = None
+
+
+def lib():
+    """Load libexs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libexs.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.exs_version.restype = C.c_char_p
+        L.exs_last_error.restype = C.c_char_p
+        L.exs_load_pocket_grid.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                           vp, C.c_int, C.c_int, vp, C.POINTER(i32)]
+        L.exs_unload_pocket.argtypes = [i32]
+        L.exs_upload_ligands.argtypes = [C.POINTER(exs_ligand_batch), vp, C.POINTER(i64)]
+        L.exs_release_ligands.argtypes = [i64]
+        L.exs_pack_topology.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, C.c_int, vp, C.c_int,
+                                        vp, vp, vp, vp]
+        L.exs_dock_batch.argtypes = [i64, C.POINTER(exs_search_params), vp, C.POINTER(i64)]
+        L.exs_get_best_poses.argtypes = [i64, C.c_int, vp, vp, vp, vp]
+        L.exs_get_orientation_results.argtypes = [i64, vp, vp]
+        L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
+        L.exs_release_job.argtypes = [i64]
+        for name in SYMBOLS:
+            getattr(L, name).restype = getattr(L, name).restype or C.c_int
+        L.exs_version.restype = C.c_char_p
+        L.exs_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != EXS_OK:
+        raise ExsError(rc, lib().exs_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def exs_version() -> str:
+    return lib().exs_version().decode()
+
+
+def exs_load_pocket_grid(values, spacing: float, origin, storage: int = EXS_F32,
+                         stream=None) -> int:
+    """values: float32 [C][nz][ny][nx] numpy array (host) or torch tensor on the GPU."""
+    org = np.ascontiguousarray(origin, dtype=np.float64)
+    pid = C.c_int32()
+    if hasattr(values, "is_cuda") and values.is_cuda:
+        v = values.contiguous()
+        c, nz, ny, nx = v.shape
+        _check(lib().exs_load_pocket_grid(C.c_void_p(v.data_ptr()), nx, ny, nz, c, float(spacing),
+                                          _p(org), int(storage), 1, _stream(stream), C.byref(pid)))
+    else:
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        c, nz, ny, nx = v.shape
+        _check(lib().exs_load_pocket_grid(_p(v), nx, ny, nz, c, float(spacing), _p(org),
+                                          int(storage), 0, _stream(stream), C.byref(pid)))
+    return pid.value
+
+
+def exs_unload_pocket(pocket_id: int):
+    _check(lib().exs_unload_pocket(int(pocket_id)))
+
+
+def exs_upload_ligands(batch, pocket_ids=None, stream=None) -> int:
+    """batch: CSR arrays (attributes atom_offset, x, y, z, type, bond_offset, bond_ij,
+    rot_offset, rot_bond, pocket_id).  pocket_ids, if given, maps batch.pocket_id values
+    (pocket indices) to loaded pocket handles."""
+    arr = lambda a, t: np.ascontiguousarray(a, dtype=t)
+    ao = arr(batch.atom_offset, np.int32)
+    x, y, z = arr(batch.x, np.float32), arr(batch.y, np.float32), arr(batch.z, np.float32)
+    ty = arr(batch.type, np.uint8)
+    bo, bij = arr(batch.bond_offset, np.int32), arr(batch.bond_ij, np.int32)
+    ro, rb = arr(batch.rot_offset, np.int32), arr(batch.rot_bond, np.int32)
+    pk = np.asarray(batch.pocket_id, dtype=np.int64)
+    if pocket_ids is not None:
+        pk = np.asarray(pocket_ids, dtype=np.int64)[pk]
+    pk = arr(pk, np.int32)
+    s = exs_ligand_batch(int(ao.shape[0] - 1), _p(ao), _p(x), _p(y), _p(z), _p(ty), _p(bo),
+                         _p(bij), _p(ro), _p(rb), _p(pk))
+    out = C.c_int64()
+    _check(lib().exs_upload_ligands(C.byref(s), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def exs_release_ligands(batch_id: int):
+    _check(lib().exs_release_ligands(int(batch_id)))
+
+
+def exs_pack_topology(lig, channels: int) -> dict:
+    """Host-only packed topology of one ligand (xyz, types, bonds, rot attributes)."""
+    xyz = np.ascontiguousarray(lig.xyz, dtype=np.float32)
+    x, y, z = (np.ascontiguousarray(xyz[:, a]) for a in range(3))
+    t = np.ascontiguousarray(lig.types, dtype=np.uint8)
+    b = np.ascontiguousarray(lig.bonds, dtype=np.int32).reshape(-1)
+    r = np.ascontiguousarray(lig.rot, dtype=np.int32)
+    n, nr = int(xyz.shape[0]), int(r.size)
+    excl = np.zeros((n, 4), np.uint32)
+    uv = np.zeros((nr, 2), np.int32)
+    mv = np.zeros((nr, 4), np.uint32)
+    _check(lib().exs_pack_topology(n, _p(x), _p(y), _p(z), _p(t), int(channels), b.size // 2, _p(b),
+                                   nr, _p(r), _p(excl), _p(uv), _p(mv)))
+
+    def rows(words, count):
+        bits = np.unpackbits(words.astype("<u4").view(np.uint8).reshape(words.shape[0], -1),
+                             axis=1, bitorder="little")
+        return bits[:, :count].astype(bool)
+
+    return dict(excl=rows(excl, n), rot_u=uv[:, 0].copy(), rot_v=uv[:, 1].copy(),
+                moving=rows(mv, n) if nr else np.zeros((0, n), bool))
+
+
+def search_params(n_orient: int, torsion_steps: int, passes: int, n_offsets: int,
+                  offset_step_A: float = 0.5, clash_cutoff_A: float = 2.0,
+                  clash_penalty: float = 1.0, top_k: int = 0, poses_per_lane: int = 0,
+                  ligands_per_wg: int = 0, flags: int = 0) -> exs_search_params:
+    return exs_search_params(n_orient, torsion_steps, passes, n_offsets, offset_step_A,
+                             clash_cutoff_A, clash_penalty, top_k, poses_per_lane,
+                             ligands_per_wg, flags)
+
+
+def exs_dock_batch(batch_id: int, params: exs_search_params, stream=None) -> int:
+    out = C.c_int64()
+    _check(lib().exs_dock_batch(int(batch_id), C.byref(params), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def exs_get_best_poses(job: int, n_ligands: int, n_atoms: int, top_k: int = 0, wait: bool = True,
+                       coords: bool = True) -> dict:
+    best = np.zeros(n_ligands, np.float32)
+    desc = np.zeros(n_ligands, POSE_DESC)
+    xyz = np.zeros((n_atoms, 3), np.float32) if coords else None
+    tk = np.zeros(n_ligands * top_k, POSE_DESC) if top_k > 0 else None
+    _check(lib().exs_get_best_poses(int(job), 1 if wait else 0, _p(best), _p(desc), _p(xyz),
+                                    _p(tk)))
+    return dict(best_score=best, desc=desc, coords=xyz,
+                topk=None if tk is None else tk.reshape(n_ligands, top_k))
+
+
+def exs_get_orientation_results(job: int, n_ligands: int, n_orient: int) -> dict:
+    sc = np.zeros(n_ligands * n_orient, np.float32)
+    desc = np.zeros(n_ligands * n_orient, POSE_DESC)
+    _check(lib().exs_get_orientation_results(int(job), _p(sc), _p(desc)))
+    return dict(score=sc.reshape(n_ligands, n_orient), desc=desc.reshape(n_ligands, n_orient))
+
+
+def exs_job_elapsed_ms(job: int) -> float:
+    ms = C.c_float()
+    _check(lib().exs_job_elapsed_ms(int(job), C.byref(ms)))
+    return float(ms.value)
+
+
+def exs_release_job(job: int):
+    _check(lib().exs_release_job(int(job)))

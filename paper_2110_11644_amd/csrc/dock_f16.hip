@@ -1,0 +1,32 @@
+// Instantiates the dock kernel for FP16 texels.
+#include "dock_kernels.inc"
+
+namespace exs {
+
+hipError_t launch_dock_f16(const DockArgs& a, int ppl, dim3 grid, dim3 block, size_t lds,
+                           hipStream_t st) {
+#define EXS_LAUNCH(SS, PP) \
+    if (a.S == SS && ppl == PP) { \
+        hipLaunchKernelGGL((dock_kernel<SS, PP, TexF16>), grid, block, lds, st, a); \
+        return hipGetLastError(); \
+    }
+    EXS_LAUNCH(8, 1) EXS_LAUNCH(8, 2) EXS_LAUNCH(16, 1) EXS_LAUNCH(16, 2) EXS_LAUNCH(32, 1) EXS_LAUNCH(32, 2)
+#undef EXS_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+const void* dock_kernel_fn_f16(int S, int ppl) {
+#define EXS_FN(SS, PP) \
+    if (S == SS && ppl == PP) return reinterpret_cast<const void*>(&dock_kernel<SS, PP, TexF16>);
+    EXS_FN(8, 1) EXS_FN(8, 2) EXS_FN(16, 1) EXS_FN(16, 2) EXS_FN(32, 1) EXS_FN(32, 2)
+#undef EXS_FN
+    return nullptr;
+}
+
+hipError_t upload_trig_f16(const float* t32, const double* t64) {
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_trig32), t32, sizeof(float) * kTrigEntries);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_trig64), t64, sizeof(double) * kTrigEntries);
+}
+
+}  // namespace exs

@@ -1,0 +1,98 @@
+// Small kernels (grid conversion, counter reset) and the dispatch of the dock
+// launches over texel storage types.
+#include <math.h>
+
+#include "exs_internal.h"
+
+namespace exs {
+
+hipError_t launch_dock_f32(const DockArgs& a, int ppl, dim3 grid, dim3 block, size_t lds, hipStream_t st);
+hipError_t launch_dock_bf16(const DockArgs& a, int ppl, dim3 grid, dim3 block, size_t lds, hipStream_t st);
+hipError_t launch_dock_f16(const DockArgs& a, int ppl, dim3 grid, dim3 block, size_t lds, hipStream_t st);
+const void* dock_kernel_fn_f32(int S, int ppl);
+const void* dock_kernel_fn_bf16(int S, int ppl);
+const void* dock_kernel_fn_f16(int S, int ppl);
+hipError_t upload_trig_f32(const float* t32, const double* t64);
+hipError_t upload_trig_bf16(const float* t32, const double* t64);
+hipError_t upload_trig_f16(const float* t32, const double* t64);
+
+
+
+// FP32 -> 16-bit texels, round to nearest even.
+__global__ void convert_grid_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                    int64_t count, int storage) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = src[i];
+        if (storage == 1) {                       // BF16
+            uint32_t u = __builtin_bit_cast(uint32_t, v);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            dst[i] = (uint16_t)(u >> 16);
+        } else {                                  // FP16
+            dst[i] = __builtin_bit_cast(uint16_t, (_Float16)v);
+        }
+    }
+}
+
+// Zero a small int array with a kernel (safe inside a captured graph).
+__global__ void zero_ints_kernel(int* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
+                       size_t lds, hipStream_t st) {
+    dim3 grid(n_blocks), block(threads);
+    switch (storage) {
+        case 0: return launch_dock_f32(a, ppl, grid, block, lds, st);
+        case 1: return launch_dock_bf16(a, ppl, grid, block, lds, st);
+        case 2: return launch_dock_f16(a, ppl, grid, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+const void* dock_kernel_fn(int storage, int S, int ppl) {
+    switch (storage) {
+        case 0: return dock_kernel_fn_f32(S, ppl);
+        case 1: return dock_kernel_fn_bf16(S, ppl);
+        case 2: return dock_kernel_fn_f16(S, ppl);
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_convert_grid(const float* src, uint16_t* dst, int64_t count, int storage,
+                               hipStream_t st) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(convert_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst,
+                       count, storage);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// Fill the turn tables of the current device from FP64 host values.
+hipError_t upload_trig_tables() {
+    float t32[kTrigEntries];
+    double t64[kTrigEntries];
+    const int steps[3] = {8, 16, 32};
+    for (int si = 0; si < 3; ++si) {
+        int S = steps[si], off = trig_offset(S);
+        for (int s = 0; s < S; ++s) {
+            double a = 2.0 * 3.14159265358979323846 * (double)s / (double)S;
+            double c = s == 0 ? 1.0 : cos(a), sn = s == 0 ? 0.0 : sin(a);
+            t64[off + s] = c; t64[off + S + s] = sn;
+            t32[off + s] = (float)c; t32[off + S + s] = (float)sn;
+        }
+    }
+    hipError_t e = upload_trig_f32(t32, t64);
+    if (e == hipSuccess) e = upload_trig_bf16(t32, t64);
+    if (e == hipSuccess) e = upload_trig_f16(t32, t64);
+    return e;
+}
+
+}  // namespace exs

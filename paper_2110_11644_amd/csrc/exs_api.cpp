@@ -1,0 +1,837 @@
+// C ABI of libexs: pocket registry, ligand-batch upload, dock jobs.
+//
+// Host work is limited to validation, topology packing at upload time and
+// launch bookkeeping; every step of the search itself runs in the HIP kernels
+// (dock_kernels.hip).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "exs.h"
+#include "exs_internal.h"
+#include "exs_pack.h"
+
+using namespace exs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? EXS_ENOMEM : EXS_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+// ---- per-device state -------------------------------------------------------------------------
+
+struct DeviceState {
+    bool ready = false;
+    int cus = 0;
+    std::map<int, std::pair<float*, double*>> orient_tables;   // K -> (FP32, FP64) [K][9]
+};
+
+std::mutex g_dev_mu;
+std::unordered_map<int, DeviceState> g_dev;
+
+int current_device(int* dev) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return fail(EXS_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    return EXS_OK;
+}
+
+int ensure_device(int dev) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceState& d = g_dev[dev];
+    if (d.ready) return EXS_OK;
+    HIP_TRY(upload_trig_tables());
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    d.cus = prop.multiProcessorCount;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    d.ready = true;
+    return EXS_OK;
+}
+
+// Fibonacci-sphere orientations R_k = Rz(phi_k) Ry(beta_k): z_k = 1 - (2k+1)/K,
+// beta_k = acos z_k, phi_k = k * golden angle; R_k maps +z to the k-th sphere point.
+int orientation_tables(int dev, int K, const float** r32, const double** r64) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceState& d = g_dev[dev];
+    auto it = d.orient_tables.find(K);
+    if (it == d.orient_tables.end()) {
+        std::vector<double> h64((size_t)K * 9);
+        std::vector<float> h32((size_t)K * 9);
+        const double golden = M_PI * (3.0 - sqrt(5.0));
+        for (int k = 0; k < K; ++k) {
+            double zk = 1.0 - (2.0 * k + 1.0) / (double)K;
+            double beta = acos(zk), phi = (double)k * golden;
+            double cb = cos(beta), sb = sin(beta), cp = cos(phi), sp = sin(phi);
+            // rows of Rz(phi) * Ry(beta)
+            double m[9] = {cp * cb, -sp, cp * sb, sp * cb, cp, sp * sb, -sb, 0.0, cb};
+            for (int t = 0; t < 9; ++t) {
+                h64[(size_t)k * 9 + t] = m[t];
+                h32[(size_t)k * 9 + t] = (float)m[t];
+            }
+        }
+        float* d32 = nullptr;
+        double* d64 = nullptr;
+        HIP_TRY(hipMalloc(&d32, h32.size() * sizeof(float)));
+        HIP_TRY(hipMalloc(&d64, h64.size() * sizeof(double)));
+        HIP_TRY(hipMemcpy(d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+        it = d.orient_tables.emplace(K, std::make_pair(d32, d64)).first;
+    }
+    *r32 = it->second.first;
+    *r64 = it->second.second;
+    return EXS_OK;
+}
+
+// ---- registries --------------------------------------------------------------------------------
+
+struct Pocket {
+    int device = 0;
+    int nx = 0, ny = 0, nz = 0, channels = 0, storage = EXS_F32;
+    double h = 0, origin[3] = {0, 0, 0};
+    float* master = nullptr;     // FP32 texels
+    uint16_t* half = nullptr;    // 16-bit texels (storage != F32)
+    GridDesc desc;
+    std::atomic<int> users{0};
+};
+
+struct Batch {
+    int device = 0;
+    int L = 0, A = 0, R = 0, n_max = 1;
+    std::vector<int32_t> pockets;          // pocket handle per table slot
+    std::vector<int> storage_of_slot;
+    std::vector<LigInfo> info;             // host copy
+    std::vector<std::vector<int16_t>> mcount;   // moving-set sizes per ligand
+    std::vector<int32_t> rot_base;
+    LigInfo* d_info = nullptr;
+    float4* d_ref = nullptr;
+    double* d_ref64 = nullptr;
+    uint4* d_excl = nullptr;
+    uint32_t* d_rot_uv = nullptr;
+    uint4* d_rot_mask = nullptr;
+    GridDesc* d_grids = nullptr;
+    std::mutex order_mu;
+    std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
+    std::map<std::vector<int>, std::vector<int>> group_sizes;
+};
+
+struct Job {
+    int device = 0;
+    std::shared_ptr<Batch> batch;
+    exs_search_params prm{};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int L = 0, A = 0, R = 0, K = 0, top_k = 0;
+    std::vector<void*> bufs;    // stream-ordered allocations
+    DockArgs args{};
+};
+
+std::mutex g_reg_mu;
+int32_t g_next_pocket = 1;
+int64_t g_next_batch = 1, g_next_job = 1;
+std::unordered_map<int32_t, std::shared_ptr<Pocket>> g_pockets;
+std::unordered_map<int64_t, std::shared_ptr<Batch>> g_batches;
+std::unordered_map<int64_t, std::shared_ptr<Job>> g_jobs;
+
+std::shared_ptr<Pocket> find_pocket(int32_t id) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    auto it = g_pockets.find(id);
+    return it == g_pockets.end() ? nullptr : it->second;
+}
+std::shared_ptr<Batch> find_batch(int64_t id) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    auto it = g_batches.find(id);
+    return it == g_batches.end() ? nullptr : it->second;
+}
+std::shared_ptr<Job> find_job(int64_t id) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    auto it = g_jobs.find(id);
+    return it == g_jobs.end() ? nullptr : it->second;
+}
+
+template <class T>
+int dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    HIP_TRY(hipMalloc((void**)dst, bytes));
+    if (count) HIP_TRY(hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+    return EXS_OK;
+}
+
+void free_batch(Batch* b) {
+    void* ptrs[] = {b->d_info, b->d_ref, b->d_ref64, b->d_excl, b->d_rot_uv, b->d_rot_mask,
+                    b->d_grids};
+    for (void* p : ptrs) if (p) (void)hipFree(p);
+    for (auto& kv : b->d_orders) (void)hipFree(kv.second);
+    b->d_orders.clear();
+}
+
+}  // namespace
+
+// ---- C ABI -------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* exs_version(void) { return "exs 0.1 (gfx950)"; }
+
+const char* exs_last_error(void) { return g_last_error.c_str(); }
+
+int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channels,
+                         double spacing_A, const double origin_A[3], int storage,
+                         int values_on_device, void* stream, int32_t* pocket_id_out) {
+    try {
+        if (!values || !origin_A || !pocket_id_out) return fail(EXS_EINVAL, "null argument");
+        if (nx < 2 || ny < 2 || nz < 2) return fail(EXS_EINVAL, "grid %dx%dx%d: each edge must be >= 2", nx, ny, nz);
+        if (channels < 1 || channels > EXS_MAX_CHANNELS)
+            return fail(EXS_EINVAL, "channels %d outside [1, %d]", channels, EXS_MAX_CHANNELS);
+        if (!(spacing_A > 0.0) || !isfinite(spacing_A)) return fail(EXS_EINVAL, "spacing must be > 0");
+        if (storage != EXS_F32 && storage != EXS_BF16 && storage != EXS_F16)
+            return fail(EXS_EINVAL, "unknown storage %d", storage);
+        const int64_t chan = (int64_t)nx * ny * nz;
+        if (chan * 4 > INT32_MAX) return fail(EXS_EINVAL, "a grid channel must be < 2 GiB");
+        const int64_t count = chan * channels;
+        if (!values_on_device) {
+            for (int64_t i = 0; i < count; ++i)
+                if (!isfinite(values[i])) return fail(EXS_EINVAL, "texel %lld is not finite", (long long)i);
+        }
+        int dev;
+        if (int rc = current_device(&dev)) return rc;
+        if (int rc = ensure_device(dev)) return rc;
+        hipStream_t st = (hipStream_t)stream;
+        auto p = std::make_shared<Pocket>();
+        p->device = dev; p->nx = nx; p->ny = ny; p->nz = nz; p->channels = channels;
+        p->storage = storage; p->h = spacing_A;
+        for (int a = 0; a < 3; ++a) p->origin[a] = origin_A[a];
+        HIP_TRY(hipMalloc(&p->master, (size_t)count * sizeof(float)));
+        HIP_TRY(hipMemcpyAsync(p->master, values, (size_t)count * sizeof(float),
+                               values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+        if (storage != EXS_F32) {
+            HIP_TRY(hipMalloc(&p->half, (size_t)count * sizeof(uint16_t)));
+            HIP_TRY(launch_convert_grid(p->master, p->half, count, storage, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        GridDesc& g = p->desc;
+        memset(&g, 0, sizeof g);
+        g.tex = storage == EXS_F32 ? (const void*)p->master : (const void*)p->half;
+        g.master = p->master;
+        g.nx = nx; g.ny = ny; g.nz = nz; g.channels = channels;
+        g.ox = (float)origin_A[0]; g.oy = (float)origin_A[1]; g.oz = (float)origin_A[2];
+        g.inv_h = (float)(1.0 / spacing_A);
+        g.h = spacing_A; g.dox = origin_A[0]; g.doy = origin_A[1]; g.doz = origin_A[2];
+        g.dcx = origin_A[0] + spacing_A * (nx - 1) / 2.0;
+        g.dcy = origin_A[1] + spacing_A * (ny - 1) / 2.0;
+        g.dcz = origin_A[2] + spacing_A * (nz - 1) / 2.0;
+        g.cx = (float)g.dcx; g.cy = (float)g.dcy; g.cz = (float)g.dcz;
+        g.chan_bytes = (int32_t)(chan * (storage == EXS_F32 ? 4 : 2));
+        g.master_chan_bytes = (int32_t)(chan * 4);
+        g.storage = storage;
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        int32_t id = g_next_pocket++;
+        g_pockets[id] = p;
+        *pocket_id_out = id;
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_unload_pocket(int32_t pocket_id) {
+    std::shared_ptr<Pocket> p;
+    {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        auto it = g_pockets.find(pocket_id);
+        if (it == g_pockets.end()) return fail(EXS_ENOENT, "unknown pocket %d", pocket_id);
+        if (it->second->users.load() > 0)
+            return fail(EXS_EINVAL, "pocket %d is used by %d uploaded batch(es)", pocket_id,
+                        it->second->users.load());
+        p = it->second;
+        g_pockets.erase(it);
+    }
+    (void)hipDeviceSynchronize();
+    if (p->master) (void)hipFree(p->master);
+    if (p->half) (void)hipFree(p->half);
+    return EXS_OK;
+}
+
+int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_out) {
+    try {
+        if (!in || !batch_out) return fail(EXS_EINVAL, "null argument");
+        const int L = in->n_ligands;
+        if (L < 0) return fail(EXS_EINVAL, "negative ligand count");
+        if (L > 0 && (!in->atom_offset || !in->x || !in->y || !in->z || !in->type ||
+                      !in->bond_offset || !in->rot_offset || !in->pocket_id))
+            return fail(EXS_EINVAL, "null array in ligand batch");
+        int dev;
+        if (int rc = current_device(&dev)) return rc;
+        if (int rc = ensure_device(dev)) return rc;
+        auto b = std::make_shared<Batch>();
+        b->device = dev;
+        b->L = L;
+        // pockets of the batch
+        std::map<int32_t, int> slot_of;
+        std::vector<std::shared_ptr<Pocket>> pk;
+        std::vector<int> lig_slot(L);
+        for (int l = 0; l < L; ++l) {
+            int32_t id = in->pocket_id[l];
+            auto it = slot_of.find(id);
+            if (it == slot_of.end()) {
+                auto p = find_pocket(id);
+                if (!p) return fail(EXS_EINVAL, "ligand %d: unknown pocket %d", l, id);
+                if (p->device != dev) return fail(EXS_EINVAL, "ligand %d: pocket %d lives on device %d", l, id, p->device);
+                it = slot_of.emplace(id, (int)pk.size()).first;
+                pk.push_back(p);
+            }
+            lig_slot[l] = it->second;
+        }
+        if (L > 0 && in->atom_offset[0] != 0) return fail(EXS_EINVAL, "atom_offset[0] must be 0");
+        if (L > 0 && (in->bond_offset[0] != 0 || in->rot_offset[0] != 0))
+            return fail(EXS_EINVAL, "bond_offset[0] and rot_offset[0] must be 0");
+        for (int l = 0; l < L; ++l)
+            if (in->atom_offset[l + 1] < in->atom_offset[l] || in->bond_offset[l + 1] < in->bond_offset[l] ||
+                in->rot_offset[l + 1] < in->rot_offset[l])
+                return fail(EXS_EINVAL, "ligand %d: offsets decrease", l);
+        const int A = L ? in->atom_offset[L] : 0;
+        const int R = L ? in->rot_offset[L] : 0;
+        if (L > 0 && in->bond_offset[L] > 0 && !in->bond_ij) return fail(EXS_EINVAL, "null bond_ij");
+        if (R > 0 && !in->rot_bond) return fail(EXS_EINVAL, "null rot_bond");
+        b->A = A; b->R = R;
+        // pack on host threads
+        std::vector<PackedLigand> packed(L);
+        std::vector<int> rc_of(L, EXS_OK);
+        std::vector<std::string> err_of(L);
+        unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        if (L < 256) nth = 1;
+        std::vector<std::thread> pool;
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (;;) {
+                int l = next.fetch_add(1);
+                if (l >= L) break;
+                int a0 = in->atom_offset[l], n = in->atom_offset[l + 1] - a0;
+                int b0 = in->bond_offset[l], nb = in->bond_offset[l + 1] - b0;
+                int r0 = in->rot_offset[l], nr = in->rot_offset[l + 1] - r0;
+                rc_of[l] = pack_ligand(n, in->bond_ij + 2 * (size_t)b0, nb, in->rot_bond + r0, nr,
+                                       in->type + a0, pk[lig_slot[l]]->channels, in->x + a0,
+                                       in->y + a0, in->z + a0, &packed[l], &err_of[l]);
+            }
+        };
+        for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work);
+        work();
+        for (auto& t : pool) t.join();
+        for (int l = 0; l < L; ++l)
+            if (rc_of[l]) return fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
+        // flatten
+        std::vector<float4> ref(A);
+        std::vector<double> ref64((size_t)A * 3);
+        std::vector<uint4> excl(A);
+        std::vector<uint32_t> ruv(R);
+        std::vector<uint4> rmask(R);
+        b->info.resize(L);
+        b->mcount.resize(L);
+        b->rot_base.resize(L);
+        for (int l = 0; l < L; ++l) {
+            const PackedLigand& p = packed[l];
+            int a0 = in->atom_offset[l], r0 = in->rot_offset[l];
+            LigInfo& inf = b->info[l];
+            memset(&inf, 0, sizeof inf);
+            inf.atom_base = a0; inf.rot_base = r0; inf.n = (int16_t)p.n; inf.nrot = (int16_t)p.nrot;
+            inf.pocket = (int16_t)lig_slot[l];
+            b->n_max = std::max(b->n_max, p.n);
+            b->rot_base[l] = r0;
+            for (int i = 0; i < p.n; ++i) {
+                double dx = (double)in->x[a0 + i] - p.centroid[0];
+                double dy = (double)in->y[a0 + i] - p.centroid[1];
+                double dz = (double)in->z[a0 + i] - p.centroid[2];
+                int t = in->type[a0 + i];
+                ref[a0 + i] = make_float4((float)dx, (float)dy, (float)dz, __builtin_bit_cast(float, t));
+                ref64[(size_t)(a0 + i) * 3 + 0] = dx;
+                ref64[(size_t)(a0 + i) * 3 + 1] = dy;
+                ref64[(size_t)(a0 + i) * 3 + 2] = dz;
+                excl[a0 + i] = p.excl[i].as_uint4();
+            }
+            b->mcount[l].resize(p.nrot);
+            for (int r = 0; r < p.nrot; ++r) {
+                ruv[r0 + r] = (uint32_t)p.rot_u[r] | ((uint32_t)p.rot_v[r] << 16);
+                rmask[r0 + r] = p.moving[r].as_uint4();
+                b->mcount[l][r] = (int16_t)p.moving[r].count();
+            }
+        }
+        std::vector<GridDesc> grids(pk.size());
+        for (size_t s = 0; s < pk.size(); ++s) {
+            grids[s] = pk[s]->desc;
+            b->storage_of_slot.push_back(pk[s]->storage);
+        }
+        hipStream_t st = (hipStream_t)stream;
+        int rc;
+        if ((rc = dev_upload(&b->d_info, b->info.data(), (size_t)L, st)) ||
+            (rc = dev_upload(&b->d_ref, ref.data(), (size_t)A, st)) ||
+            (rc = dev_upload(&b->d_ref64, ref64.data(), (size_t)A * 3, st)) ||
+            (rc = dev_upload(&b->d_excl, excl.data(), (size_t)A, st)) ||
+            (rc = dev_upload(&b->d_rot_uv, ruv.data(), (size_t)R, st)) ||
+            (rc = dev_upload(&b->d_rot_mask, rmask.data(), (size_t)R, st)) ||
+            (rc = dev_upload(&b->d_grids, grids.data(), grids.size(), st))) {
+            free_batch(b.get());
+            return rc;
+        }
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_batch(b.get());
+            return fail(EXS_EDEVICE, "upload: %s", hipGetErrorString(e));
+        }
+        for (auto& p : pk) { p->users++; b->pockets.push_back(0); }
+        for (auto& kv : slot_of) b->pockets[kv.second] = kv.first;
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        int64_t id = g_next_batch++;
+        g_batches[id] = b;
+        *batch_out = id;
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_pack_topology(int n, const float* x, const float* y, const float* z, const uint8_t* type,
+                      int channels, int nb, const int32_t* bond_ij, int nrot,
+                      const int32_t* rot_bond, uint32_t* excl, int32_t* rot_uv, uint32_t* moving) {
+    try {
+        if (!x || !y || !z || !type || (nb > 0 && !bond_ij) || (nrot > 0 && !rot_bond))
+            return fail(EXS_EINVAL, "null argument");
+        PackedLigand p;
+        std::string err;
+        int rc = pack_ligand(n, bond_ij, nb, rot_bond, nrot, type, channels, x, y, z, &p, &err);
+        if (rc) return fail(rc, "%s", err.c_str());
+        for (int i = 0; excl && i < n; ++i) {
+            uint4 w = p.excl[i].as_uint4();
+            excl[4 * i] = w.x; excl[4 * i + 1] = w.y; excl[4 * i + 2] = w.z; excl[4 * i + 3] = w.w;
+        }
+        for (int b = 0; b < nrot; ++b) {
+            if (rot_uv) { rot_uv[2 * b] = p.rot_u[b]; rot_uv[2 * b + 1] = p.rot_v[b]; }
+            if (moving) {
+                uint4 w = p.moving[b].as_uint4();
+                moving[4 * b] = w.x; moving[4 * b + 1] = w.y; moving[4 * b + 2] = w.z; moving[4 * b + 3] = w.w;
+            }
+        }
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_release_ligands(int64_t batch) {
+    std::shared_ptr<Batch> b;
+    {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        auto it = g_batches.find(batch);
+        if (it == g_batches.end()) return fail(EXS_ENOENT, "unknown batch %lld", (long long)batch);
+        for (auto& kv : g_jobs)
+            if (kv.second->batch == it->second)
+                return fail(EXS_EINVAL, "batch %lld still has job %lld", (long long)batch, (long long)kv.first);
+        b = it->second;
+        g_batches.erase(it);
+        for (int32_t id : b->pockets) {
+            auto p = g_pockets.find(id);
+            if (p != g_pockets.end()) p->second->users--;
+        }
+    }
+    free_batch(b.get());
+    return EXS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Longest-first processing order, grouped by pocket for per-pocket launches.
+int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_t st,
+                int32_t** d_order, std::vector<int>* groups) {
+    std::vector<int> key = {K, S, P, T, persistent};
+    std::lock_guard<std::mutex> lk(b.order_mu);
+    auto it = b.d_orders.find(key);
+    if (it != b.d_orders.end()) {
+        *d_order = it->second;
+        *groups = b.group_sizes[key];
+        return EXS_OK;
+    }
+    std::vector<double> cost(b.L);
+    for (int l = 0; l < b.L; ++l) {
+        cost[l] = ligand_cost(b.info[l].n, b.mcount[l].data(), b.info[l].nrot, K, S, P, T);
+        b.info[l].cost = (float)cost[l];
+    }
+    std::vector<int> ord(b.L);
+    std::iota(ord.begin(), ord.end(), 0);
+    const int n_slots = (int)b.pockets.size();
+    if (persistent) {
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+        groups->assign(1, b.L);
+    } else {
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+            if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
+            return cost[a] > cost[c];
+        });
+        groups->assign(n_slots, 0);
+        for (int l = 0; l < b.L; ++l) (*groups)[b.info[l].pocket]++;
+    }
+    int32_t* d = nullptr;
+    HIP_TRY(hipMalloc(&d, std::max(1, b.L) * sizeof(int32_t)));
+    if (b.L > 0) {
+        HIP_TRY(hipMemcpyAsync(d, ord.data(), b.L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    b.d_orders[key] = d;
+    b.group_sizes[key] = *groups;
+    *d_order = d;
+    return EXS_OK;
+}
+
+template <class T>
+int job_alloc(Job& j, T** p, size_t count, hipStream_t st) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void* q = nullptr;
+    HIP_TRY(hipMallocAsync(&q, bytes, st));
+    j.bufs.push_back(q);
+    *p = (T*)q;
+    return EXS_OK;
+}
+
+void job_free(Job& j) {
+    for (void* p : j.bufs) (void)hipFreeAsync(p, j.stream);
+    j.bufs.clear();
+    if (j.ev0) (void)hipEventDestroy(j.ev0);
+    if (j.ev1) (void)hipEventDestroy(j.ev1);
+    j.ev0 = j.ev1 = nullptr;
+}
+
+}  // namespace
+
+namespace {
+
+int job_wait(Job& j, int wait) {
+    if (!wait) {
+        hipError_t e = hipEventQuery(j.ev1);
+        if (e == hipErrorNotReady) return fail(EXS_ENOTREADY, "job still running");
+        if (e != hipSuccess) return fail(EXS_EDEVICE, "job: %s", hipGetErrorString(e));
+        return EXS_OK;
+    }
+    HIP_TRY(hipEventSynchronize(j.ev1));
+    return EXS_OK;
+}
+
+template <class T>
+int copy_out(T* dst, const T* src, size_t count) {
+    if (!dst || !count) return EXS_OK;
+    HIP_TRY(hipMemcpy(dst, src, count * sizeof(T), hipMemcpyDeviceToHost));
+    return EXS_OK;
+}
+
+void fill_desc(exs_pose_desc& d, float score, double s64, int k, int32_t tau_packed,
+                      int nrot, const uint8_t* theta, size_t theta_stride) {
+    memset(&d, 0, sizeof d);
+    d.score = score;
+    d.score_fp64 = s64;
+    d.orient = k;
+    d.tau[0] = (int8_t)(tau_packed & 0xff);
+    d.tau[1] = (int8_t)((tau_packed >> 8) & 0xff);
+    d.tau[2] = (int8_t)((tau_packed >> 16) & 0xff);
+    d.n_rot = (uint8_t)nrot;
+    for (int b = 0; b < nrot; ++b) d.theta[b] = theta[(size_t)b * theta_stride];
+}
+
+}  // namespace
+
+extern "C" {
+
+int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream, int64_t* job_out) {
+    try {
+        if (!params || !job_out) return fail(EXS_EINVAL, "null argument");
+        auto b = find_batch(batch);
+        if (!b) return fail(EXS_ENOENT, "unknown batch %lld", (long long)batch);
+        const exs_search_params& p = *params;
+        if (p.n_orient < 1 || p.n_orient > EXS_MAX_ORIENT)
+            return fail(EXS_EINVAL, "n_orient %d outside [1, %d]", p.n_orient, EXS_MAX_ORIENT);
+        if (p.torsion_steps != 8 && p.torsion_steps != 16 && p.torsion_steps != 32)
+            return fail(EXS_EINVAL, "torsion_steps %d: supported 8, 16, 32", p.torsion_steps);
+        if (p.passes < 0 || p.passes > 64) return fail(EXS_EINVAL, "passes %d outside [0, 64]", p.passes);
+        if (p.n_offsets != 1 && p.n_offsets != 27) return fail(EXS_EINVAL, "n_offsets must be 1 or 27");
+        if (!(p.offset_step_A >= 0.0f) || !(p.clash_cutoff_A >= 0.0f) || !isfinite(p.clash_penalty) ||
+            !isfinite(p.offset_step_A) || !isfinite(p.clash_cutoff_A))
+            return fail(EXS_EINVAL, "offset step, clash cutoff and penalty must be finite, >= 0");
+        if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return fail(EXS_EINVAL, "top_k %d outside [0, %d]", p.top_k, EXS_MAX_TOPK);
+        if (p.n_offsets == 27 && p.passes > 127) return fail(EXS_EINVAL, "too many passes for offsets");
+        int ppl = p.poses_per_lane ? p.poses_per_lane : 1;
+        if (ppl != 1 && ppl != 2) return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2", ppl);
+        const int K = p.n_orient;
+        const int wpl = (K + kWave * ppl - 1) / (kWave * ppl);
+        int lpw = p.ligands_per_wg;
+        if (lpw == 0) lpw = std::max(1, std::min(kMaxLpw, kMaxWavesPerWg / std::max(1, wpl) / 2));
+        if (lpw != 1 && lpw != 2 && lpw != 4 && lpw != 8)
+            return fail(EXS_EINVAL, "ligands_per_wg %d: supported 1, 2, 4, 8", lpw);
+        const int threads = lpw * wpl * kWave;
+        if (threads > kMaxThreadsPerWg)
+            return fail(EXS_EINVAL, "workgroup of %d ligands x %d waves exceeds %d threads", lpw, wpl,
+                        kMaxThreadsPerWg);
+        const int top_k = std::min(p.top_k, K);
+        const bool persistent = (p.flags & EXS_FLAG_PERSISTENT) != 0;
+        int storage = -1;
+        for (size_t s = 0; s < b->pockets.size(); ++s) {
+            auto pk = find_pocket(b->pockets[s]);
+            if (!pk) return fail(EXS_ENOENT, "pocket %d of the batch was unloaded", b->pockets[s]);
+            if (storage >= 0 && pk->storage != storage && persistent)
+                return fail(EXS_EINVAL, "persistent launch needs one texel storage for all pockets");
+            storage = storage < 0 ? pk->storage : storage;
+        }
+        int dev;
+        if (int rc = current_device(&dev)) return rc;
+        if (dev != b->device) return fail(EXS_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+        hipStream_t st = (hipStream_t)stream;
+        const float* r32;
+        const double* r64;
+        if (int rc = orientation_tables(dev, K, &r32, &r64)) return rc;
+        int32_t* d_order = nullptr;
+        std::vector<int> groups;
+        if (int rc = batch_order(*b, K, p.torsion_steps, p.passes, p.n_offsets, persistent, st,
+                                 &d_order, &groups)) return rc;
+
+        auto j = std::make_shared<Job>();
+        j->device = dev; j->batch = b; j->prm = p; j->stream = st;
+        j->L = b->L; j->A = b->A; j->R = b->R; j->K = K; j->top_k = top_k;
+        DockArgs& a = j->args;
+        memset(&a, 0, sizeof a);
+        a.info = b->d_info; a.ref = b->d_ref; a.ref64 = b->d_ref64; a.excl = b->d_excl;
+        a.rot_uv = b->d_rot_uv; a.rot_mask = b->d_rot_mask; a.grids = b->d_grids;
+        a.rot32 = r32; a.rot64 = r64;
+        a.K = K; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
+        a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
+        a.step64 = (double)p.offset_step_A;
+        a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
+        a.pen64 = (double)p.clash_penalty;
+        a.top_k = top_k; a.lpw = lpw; a.wpl = wpl; a.kp = wpl * kWave * ppl;
+        a.n_max = b->n_max;
+        const int L = b->L, R = b->R, A = b->A;
+        int rc;
+        if ((rc = job_alloc(*j, &a.orient_score, (size_t)L * K, st)) ||
+            (rc = job_alloc(*j, &a.orient_theta, (size_t)R * K, st)) ||
+            (rc = job_alloc(*j, &a.orient_tau, (size_t)L * K, st)) ||
+            (rc = job_alloc(*j, &a.best_score, (size_t)L, st)) ||
+            (rc = job_alloc(*j, &a.best_k, (size_t)L, st)) ||
+            (rc = job_alloc(*j, &a.best_coords, (size_t)A * 3, st)) ||
+            (rc = job_alloc(*j, &a.best_theta, (size_t)R, st)) ||
+            (rc = job_alloc(*j, &a.best_tau, (size_t)L, st)) ||
+            (rc = job_alloc(*j, &a.best_score64, (size_t)L, st)) ||
+            (rc = job_alloc(*j, &a.topk_k, (size_t)L * top_k, st)) ||
+            (rc = job_alloc(*j, &a.topk_score, (size_t)L * top_k, st)) ||
+            (rc = job_alloc(*j, &a.topk_score64, (size_t)L * top_k, st)) ||
+            (rc = job_alloc(*j, &a.topk_theta, (size_t)R * top_k, st)) ||
+            (rc = job_alloc(*j, &a.topk_tau, (size_t)L * top_k, st)) ||
+            (rc = job_alloc(*j, &a.tile_counter, (size_t)1, st))) {
+            job_free(*j);
+            return rc;
+        }
+        a.slot_floats = (int64_t)lpw * a.n_max * 3 * a.kp;
+        const size_t lds = dock_lds_bytes(lpw, top_k);
+        const void* fn = dock_kernel_fn(storage < 0 ? 0 : storage, a.S, ppl);
+        if (!fn) { job_free(*j); return fail(EXS_EINVAL, "no kernel for this configuration"); }
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) { job_free(*j); return fail(EXS_EDEVICE, "LDS %zu: %s", lds, hipGetErrorString(e)); }
+        }
+        // scratch: one slot per workgroup (largest launch)
+        int64_t slots = 0;
+        int resident = 0;
+        if (persistent) {
+            int per_cu = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            int cus = 0;
+            {
+                std::lock_guard<std::mutex> lk(g_dev_mu);
+                cus = g_dev[dev].cus;
+            }
+            const int n_tiles = (L + lpw - 1) / lpw;
+            resident = std::max(1, std::min(n_tiles, per_cu * cus));
+            slots = resident;
+        } else {
+            for (int gsz : groups) slots = std::max<int64_t>(slots, (gsz + lpw - 1) / lpw);
+        }
+        if ((rc = job_alloc(*j, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats, st))) {
+            job_free(*j);
+            return rc;
+        }
+        HIP_TRY(hipEventCreate(&j->ev0));
+        HIP_TRY(hipEventCreate(&j->ev1));
+        HIP_TRY(hipEventRecord(j->ev0, st));
+        if (L > 0) {
+            if (persistent) {
+                a.order = d_order;
+                a.n_order = L;
+                a.n_tiles = (L + lpw - 1) / lpw;
+                a.persistent = 1;
+                HIP_TRY(launch_zero_ints(a.tile_counter, 1, st));
+                HIP_TRY(launch_dock(a, storage, ppl, resident, threads, lds, st));
+            } else {
+                int start = 0;
+                for (size_t gi = 0; gi < groups.size(); ++gi) {
+                    const int gsz = groups[gi];
+                    if (gsz == 0) continue;
+                    DockArgs ga = a;
+                    ga.order = d_order + start;
+                    ga.n_order = gsz;
+                    ga.n_tiles = (gsz + lpw - 1) / lpw;
+                    ga.persistent = 0;
+                    HIP_TRY(launch_dock(ga, b->storage_of_slot[gi], ppl, ga.n_tiles, threads, lds, st));
+                    start += gsz;
+                }
+            }
+        }
+        HIP_TRY(hipEventRecord(j->ev1, st));
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        int64_t id = g_next_job++;
+        g_jobs[id] = j;
+        *job_out = id;
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_get_best_poses(int64_t job, int wait, float* best_score, exs_pose_desc* desc, float* coords,
+                       exs_pose_desc* topk) {
+    try {
+        auto j = find_job(job);
+        if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+        if (int rc = job_wait(*j, wait)) return rc;
+        const DockArgs& a = j->args;
+        const int L = j->L, R = j->R, tk = j->top_k;
+        if (best_score && tk > 0) {
+            std::vector<double> b64(L);
+            if (int rc = copy_out(b64.data(), a.best_score64, (size_t)L)) return rc;
+            for (int l = 0; l < L; ++l) best_score[l] = (float)b64[l];
+        } else if (int rc = copy_out(best_score, a.best_score, (size_t)L)) {
+            return rc;
+        }
+        if (int rc = copy_out(coords, a.best_coords, (size_t)j->A * 3)) return rc;
+        if (desc) {
+            std::vector<float> bs(L);
+            std::vector<int32_t> bk(L), bt(L);
+            std::vector<uint8_t> th(R);
+            std::vector<double> b64(L, NAN);
+            if (int rc = copy_out(bs.data(), a.best_score, (size_t)L)) return rc;
+            if (int rc = copy_out(bk.data(), a.best_k, (size_t)L)) return rc;
+            if (int rc = copy_out(bt.data(), a.best_tau, (size_t)L)) return rc;
+            if (int rc = copy_out(th.data(), a.best_theta, (size_t)R)) return rc;
+            if (tk > 0)
+                if (int rc = copy_out(b64.data(), a.best_score64, (size_t)L)) return rc;
+            for (int l = 0; l < L; ++l) {
+                const LigInfo& inf = j->batch->info[l];
+                fill_desc(desc[l], bs[l], b64[l], bk[l], bt[l], inf.nrot, th.data() + inf.rot_base, 1);
+            }
+        }
+        if (topk && tk > 0) {
+            std::vector<int32_t> kk((size_t)L * tk), tt((size_t)L * tk);
+            std::vector<float> sc((size_t)L * tk);
+            std::vector<double> s64((size_t)L * tk);
+            std::vector<uint8_t> th((size_t)R * tk);
+            if (int rc = copy_out(kk.data(), a.topk_k, kk.size())) return rc;
+            if (int rc = copy_out(tt.data(), a.topk_tau, tt.size())) return rc;
+            if (int rc = copy_out(sc.data(), a.topk_score, sc.size())) return rc;
+            if (int rc = copy_out(s64.data(), a.topk_score64, s64.size())) return rc;
+            if (int rc = copy_out(th.data(), a.topk_theta, th.size())) return rc;
+            for (int l = 0; l < L; ++l) {
+                const LigInfo& inf = j->batch->info[l];
+                for (int t = 0; t < tk; ++t) {
+                    size_t o = (size_t)l * tk + t;
+                    fill_desc(topk[o], sc[o], s64[o], kk[o], tt[o], inf.nrot,
+                              th.data() + (size_t)inf.rot_base * tk + t, (size_t)tk);
+                }
+            }
+        }
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_get_orientation_results(int64_t job, float* score, exs_pose_desc* desc) {
+    try {
+        auto j = find_job(job);
+        if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+        if (int rc = job_wait(*j, 1)) return rc;
+        const DockArgs& a = j->args;
+        const int L = j->L, K = j->K, R = j->R;
+        std::vector<float> sc((size_t)L * K);
+        if (int rc = copy_out(sc.data(), a.orient_score, sc.size())) return rc;
+        if (score) memcpy(score, sc.data(), sc.size() * sizeof(float));
+        if (desc) {
+            std::vector<int32_t> tt((size_t)L * K);
+            std::vector<uint8_t> th((size_t)R * K);
+            if (int rc = copy_out(tt.data(), a.orient_tau, tt.size())) return rc;
+            if (int rc = copy_out(th.data(), a.orient_theta, th.size())) return rc;
+            for (int l = 0; l < L; ++l) {
+                const LigInfo& inf = j->batch->info[l];
+                for (int k = 0; k < K; ++k) {
+                    size_t o = (size_t)l * K + k;
+                    fill_desc(desc[o], sc[o], NAN, k, tt[o], inf.nrot,
+                              th.data() + (size_t)inf.rot_base * K + k, (size_t)K);
+                }
+            }
+        }
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_job_elapsed_ms(int64_t job, float* ms) {
+    auto j = find_job(job);
+    if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+    if (!ms) return fail(EXS_EINVAL, "null argument");
+    if (int rc = job_wait(*j, 1)) return rc;
+    HIP_TRY(hipEventElapsedTime(ms, j->ev0, j->ev1));
+    return EXS_OK;
+}
+
+int exs_release_job(int64_t job) {
+    std::shared_ptr<Job> j;
+    {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        auto it = g_jobs.find(job);
+        if (it == g_jobs.end()) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+        j = it->second;
+        g_jobs.erase(it);
+    }
+    job_free(*j);
+    return EXS_OK;
+}
+
+}  // extern "C"

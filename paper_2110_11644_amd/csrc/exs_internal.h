@@ -1,0 +1,121 @@
+// Internal layout shared by the host runtime and the HIP kernels of libexs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exs {
+
+constexpr int kWave = 64;
+constexpr int kMaxAtoms = 128;   // bits of one exclusion / moving mask row
+constexpr int kMaxRot = 32;
+constexpr int kMaxTopK = 32;
+constexpr int kMaxLpw = 8;       // ligands per workgroup
+constexpr int kMaxWavesPerWg = 8;
+constexpr int kMaxThreadsPerWg = kMaxWavesPerWg * kWave;
+
+// Turn tables: for S in {8, 16, 32}, cos then sin of 2*pi*s/S at offset trig_offset(S).
+constexpr int kTrigEntries = 2 * (8 + 16 + 32);
+__host__ __device__ constexpr int trig_offset(int S) { return S == 8 ? 0 : (S == 16 ? 16 : 48); }
+
+// One packed ligand (caller order).
+struct LigInfo {
+    int32_t atom_base;   // first atom in the packed atom arrays
+    int32_t rot_base;    // first rotatable bond in the packed bond arrays
+    int16_t n;           // atoms
+    int16_t nrot;        // rotatable bonds
+    int16_t pocket;      // index into the job's pocket table
+    int16_t pad;
+    float cost;          // relative search cost, for longest-first ordering
+    int32_t pad2[3];
+};
+static_assert(sizeof(LigInfo) == 32, "LigInfo layout");
+
+// One pocket as the kernels see it.
+struct GridDesc {
+    const void* tex;       // storage texels [C][nz][ny][nx] (FP32, BF16 or FP16)
+    const float* master;   // FP32 master texels, same layout
+    int nx, ny, nz, channels;
+    float ox, oy, oz, inv_h;   // origin and 1/spacing, FP32
+    float cx, cy, cz, pad;     // pocket centre (grid centre), FP32
+    double h, dox, doy, doz;   // FP64 geometry for the rescoring
+    double dcx, dcy, dcz, dpad;
+    int32_t chan_bytes;        // bytes of one storage channel
+    int32_t master_chan_bytes; // bytes of one FP32 channel
+    int32_t storage;           // EXS_F32 / EXS_BF16 / EXS_F16
+    int32_t pad3;
+};
+
+// Everything one dock launch reads and writes.
+struct DockArgs {
+    // packed ligand batch
+    const LigInfo* info;
+    const float4* ref;        // [A] centred input coords, type in .w (int bits)
+    const double* ref64;      // [A*3] centred input coords in FP64 (rescoring)
+    const uint4* excl;        // [A] bit j: pair (i, j) excluded (bond distance <= 3, or i == j)
+    const uint32_t* rot_uv;   // [R] u | v << 16, u on atom 0's side
+    const uint4* rot_mask;    // [R] atoms that turn with the bond
+    const int32_t* order;     // ligands in processing order (longest first)
+    int32_t n_order;          // ligands in this launch
+    int32_t n_tiles;          // ceil(n_order / lpw)
+    // pockets
+    const GridDesc* grids;
+    // search settings
+    const float* rot32;       // [K][9] orientation matrices, row-major
+    const double* rot64;      // [K][9]
+    int32_t K, S, P, T;
+    float step, cut2, pen, pad0;
+    double step64, cut2_64, pen64;
+    int32_t top_k;
+    int32_t lpw;              // ligands per workgroup
+    int32_t wpl;              // waves per ligand = ceil(K / (64 * ppl))
+    int32_t kp;               // padded orientations per ligand = wpl * 64 * ppl
+    int32_t n_max;            // atoms of the largest ligand in the launch
+    int32_t persistent;
+    // per-workgroup-slot scratch of pose coordinates: [lpw][n_max][3][kp] floats
+    float* scratch;
+    int64_t slot_floats;
+    int32_t* tile_counter;    // persistent launches: next tile to take
+    // outputs (indexed by caller ligand / rotatable-bond index)
+    float* orient_score;      // [L*K]
+    uint8_t* orient_theta;    // [R*K], element (rot_base+b)*K + k
+    int32_t* orient_tau;      // [L*K], tau packed as 3 signed bytes
+    float* best_score;        // [L]
+    int32_t* best_k;          // [L]
+    float* best_coords;       // [A*3]
+    uint8_t* best_theta;      // [R]
+    int32_t* best_tau;        // [L]
+    double* best_score64;     // [L]   (top_k > 0)
+    int32_t* topk_k;          // [L*top_k]
+    float* topk_score;        // [L*top_k] FP32 search score
+    double* topk_score64;     // [L*top_k]
+    uint8_t* topk_theta;      // [R*top_k], element (rot_base+b)*top_k + t
+    int32_t* topk_tau;        // [L*top_k]
+};
+
+// Per-ligand LDS staging of a tile (topology read wave-uniformly by the search).
+struct LigLds {
+    float4 ref[kMaxAtoms];     // centred reference coordinates, type in .w
+    uint4 excl[kMaxAtoms];     // exclusion rows
+    uint4 rmask[kMaxRot];      // moving masks
+    uint32_t ruv[kMaxRot];     // u | v << 16
+    int32_t lig, n, nrot, pocket;
+    int32_t atom_base, rot_base, pad0, pad1;
+    int32_t topk[kMaxTopK];
+};
+
+// Dynamic LDS bytes of a dock launch.
+inline size_t dock_lds_bytes(int lpw, int top_k) {
+    return (size_t)lpw * sizeof(LigLds) + (top_k > 0 ? (size_t)lpw * kMaxAtoms * 3 * sizeof(double) : 0);
+}
+
+// Launchers (dock_kernels.hip).
+hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
+                       size_t lds, hipStream_t st);
+hipError_t launch_convert_grid(const float* src, uint16_t* dst, int64_t count, int storage,
+                               hipStream_t st);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+hipError_t upload_trig_tables();
+const void* dock_kernel_fn(int storage, int S, int ppl);
+
+}  // namespace exs

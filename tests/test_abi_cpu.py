@@ -1,0 +1,110 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry
+point, and its host-side topology packing (validation, exclusion and moving
+masks) agrees with closed forms and with the oracle's independent BFS."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import exs_synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2110_11644_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2110_11644_amd import build
+        build.build()
+    binding.lib()
+    return binding
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "exs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(B):
+    decl = declared_symbols()
+    assert len(decl) >= 10
+    L = B.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(B.SYMBOLS)
+    assert "gfx950" in B.exs_version()
+
+
+class Lig:
+    def __init__(self, xyz, types, bonds, rot=()):
+        self.xyz = np.asarray(xyz, np.float32)
+        self.types = np.asarray(types, np.uint8)
+        self.bonds = np.asarray(bonds, np.int32).reshape(-1, 2)
+        self.rot = np.asarray(rot, np.int32)
+
+
+def chain(n, rot=()):
+    return Lig(np.arange(3 * n, dtype=np.float32).reshape(n, 3), np.zeros(n),
+               [[a, a + 1] for a in range(n - 1)], rot)
+
+
+def test_chain_exclusions_closed_form(B):
+    for n in (4, 5, 8, 40, 128):
+        t = B.exs_pack_topology(chain(n), 1)
+        ex = t["excl"]
+        assert ex.shape == (n, n)
+        i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        assert np.array_equal(ex, np.abs(i - j) <= 3)
+
+
+def test_moving_sets_closed_form(B):
+    t = B.exs_pack_topology(chain(6, rot=[1, 3]), 1)
+    assert t["rot_u"].tolist() == [1, 3] and t["rot_v"].tolist() == [2, 4]
+    assert np.flatnonzero(t["moving"][0]).tolist() == [3, 4, 5]
+    assert np.flatnonzero(t["moving"][1]).tolist() == [5]
+    rev = Lig(np.zeros((4, 3)), np.zeros(4), [[2, 1], [0, 1], [3, 2]], [0])
+    t = B.exs_pack_topology(rev, 1)
+    assert (t["rot_u"][0], t["rot_v"][0]) == (1, 2)
+    assert np.flatnonzero(t["moving"][0]).tolist() == [3]
+
+
+def test_packing_matches_oracle_bfs(B, oracle_lib):
+    O = oracle_lib
+    for lig in S.make_ligands("batched", 0, 40):
+        t = B.exs_pack_topology(lig, 8)
+        d = O.bond_distances(lig.n, lig.bonds)
+        assert np.array_equal(t["excl"], (d >= 0) & (d <= 3))
+        u, v, m = O.rot_topology(lig.n, lig.bonds, lig.rot)
+        assert np.array_equal(t["rot_u"], u) and np.array_equal(t["rot_v"], v)
+        assert np.array_equal(t["moving"], m)
+
+
+@pytest.mark.parametrize("case", ["ring", "type", "bond_index", "rot_index", "too_many_atoms",
+                                  "too_many_rot", "self_bond", "not_finite", "disconnected_rot"])
+def test_invalid_ligands_are_rejected(B, case):
+    lig = chain(6, rot=[2])
+    channels = 2
+    if case == "ring":
+        lig = Lig(np.zeros((4, 3)), np.zeros(4), [[0, 1], [1, 2], [2, 0], [2, 3]], [0])
+    elif case == "type":
+        lig.types[3] = 2
+    elif case == "bond_index":
+        lig.bonds[2, 1] = 6
+    elif case == "rot_index":
+        lig.rot = np.array([5], np.int32)
+    elif case == "too_many_atoms":
+        lig = chain(129)
+    elif case == "too_many_rot":
+        lig = chain(40, rot=list(range(1, 35)))
+    elif case == "self_bond":
+        lig.bonds[1] = [2, 2]
+    elif case == "not_finite":
+        lig.xyz[1, 2] = np.nan
+    elif case == "disconnected_rot":
+        lig = Lig(np.zeros((5, 3)), np.zeros(5), [[0, 1], [2, 3], [3, 4]], [2])
+    with pytest.raises(B.ExsError) as ei:
+        B.exs_pack_topology(lig, channels)
+    assert ei.value.code == B.EXS_EINVAL
