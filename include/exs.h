@@ -224,6 +224,59 @@ int exs_job_elapsed_ms(int64_t job, float* ms);
 /* Free a job's device results. */
 int exs_release_job(int64_t job);
 
+/* ---- serving: continuous batching of docking requests -------------------
+ *
+ * A server keeps a set of resident pockets and an arena of device memory
+ * (sized by hbm_budget_bytes) for admitted requests.  A request is a ligand
+ * batch (exs_ligand_batch, pocket_id = handles of the server's pockets); it is
+ * validated and packed on the submitting thread (an invalid request fails
+ * alone with EXS_EINVAL and nothing is queued), queued, admitted when its
+ * ligands fit in the arena (FIFO; a request that does not fit waits: this is
+ * the backpressure of the budget), and docked by iteration launches of the
+ * persistent kernel over the not-yet-docked ligands of every admitted request
+ * (up to max_iter_ligands per launch, up to max_inflight_iters launches in
+ * flight on separate streams, so requests arriving while others run join the
+ * next launch and overlap on the device).  Results do not depend on what a
+ * request is batched with.  Mirrors the paper's staged pipeline with queues
+ * and several GPU workers per device (Sec. 3.2, 4.3).
+ */
+typedef struct {
+    int64_t hbm_budget_bytes;   /* device memory for scratch + the request arena (0: 2 GiB) */
+    int32_t max_iter_ligands;   /* ligands per iteration launch (0: two waves of workgroups)  */
+    int32_t max_inflight_iters; /* 1 or 2 (0: 2)                                             */
+    int32_t max_arena_ligands;  /* cap on the arena's ligand slots (0: from the budget)       */
+    int32_t pad;
+} exs_server_config;
+
+typedef struct {
+    int64_t submitted, completed, queued, inflight;
+    int64_t iterations, ligands_docked;
+    int64_t arena_ligands, arena_atoms;   /* arena capacity */
+    double busy_ms;                       /* summed wall time of iteration launches */
+} exs_server_stats;
+
+/* Start a server on the current device for the given pockets (same texel
+ * storage) and search settings.  Errors: EXS_EINVAL, EXS_ENOMEM (budget below
+ * the fixed iteration scratch), EXS_EDEVICE. */
+int exs_server_create(const int32_t* pocket_ids, int n_pockets, const exs_search_params* params,
+                      const exs_server_config* cfg, int64_t* server_out);
+
+/* Queue one request (host arrays, copied).  EXS_ENOMEM if it can never fit in
+ * the arena.  request_out receives its handle. */
+int exs_server_submit(int64_t server, const exs_ligand_batch* request, int64_t* request_out);
+
+/* Results of a request: best_score [L], desc [L], coords [A*3] (any may be
+ * NULL) and its latency (submit to completion, ms).  wait = 0 gives
+ * EXS_ENOTREADY while it is queued or running.  A successful poll releases
+ * the request. */
+int exs_server_poll(int64_t server, int64_t request, int wait, float* best_score,
+                    exs_pose_desc* desc, float* coords, double* latency_ms);
+
+int exs_server_get_stats(int64_t server, exs_server_stats* out);
+
+/* Stop the server: queued requests are dropped, running launches finish. */
+int exs_server_destroy(int64_t server);
+
 #ifdef __cplusplus
 }
 #endif

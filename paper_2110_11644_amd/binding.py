@@ -26,7 +26,9 @@ STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
 # exported symbols (kept in step with include/exs.h)
 SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
            "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
-           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job")
+           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job",
+           "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
+           "exs_server_destroy")
 
 
 class ExsError(RuntimeError):
@@ -48,6 +50,18 @@ class exs_search_params(C.Structure):
                 ("clash_cutoff_A", C.c_float), ("clash_penalty", C.c_float),
                 ("top_k", C.c_int32), ("poses_per_lane", C.c_int32),
                 ("ligands_per_wg", C.c_int32), ("flags", C.c_int32)]
+
+
+class exs_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_iter_ligands", C.c_int32),
+                ("max_inflight_iters", C.c_int32), ("max_arena_ligands", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class exs_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64),
+                ("inflight", C.c_int64), ("iterations", C.c_int64), ("ligands_docked", C.c_int64),
+                ("arena_ligands", C.c_int64), ("arena_atoms", C.c_int64), ("busy_ms", C.c_double)]
 
 
 # numpy view of exs_pose_desc (56 bytes, natural alignment)
@@ -81,6 +95,12 @@ def lib():
         L.exs_get_orientation_results.argtypes = [i64, vp, vp]
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
+        L.exs_server_create.argtypes = [vp, C.c_int, C.POINTER(exs_search_params),
+                                        C.POINTER(exs_server_config), C.POINTER(i64)]
+        L.exs_server_submit.argtypes = [i64, C.POINTER(exs_ligand_batch), C.POINTER(i64)]
+        L.exs_server_poll.argtypes = [i64, i64, C.c_int, vp, vp, vp, C.POINTER(C.c_double)]
+        L.exs_server_get_stats.argtypes = [i64, C.POINTER(exs_server_stats)]
+        L.exs_server_destroy.argtypes = [i64]
         for name in SYMBOLS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.exs_version.restype = C.c_char_p
@@ -132,10 +152,8 @@ def exs_unload_pocket(pocket_id: int):
     _check(lib().exs_unload_pocket(int(pocket_id)))
 
 
-def exs_upload_ligands(batch, pocket_ids=None, stream=None) -> int:
-    """batch: CSR arrays (attributes atom_offset, x, y, z, type, bond_offset, bond_ij,
-    rot_offset, rot_bond, pocket_id).  pocket_ids, if given, maps batch.pocket_id values
-    (pocket indices) to loaded pocket handles."""
+def _batch_struct(batch, pocket_ids=None):
+    """CSR arrays -> (exs_ligand_batch, keep-alive arrays)."""
     arr = lambda a, t: np.ascontiguousarray(a, dtype=t)
     ao = arr(batch.atom_offset, np.int32)
     x, y, z = arr(batch.x, np.float32), arr(batch.y, np.float32), arr(batch.z, np.float32)
@@ -146,8 +164,17 @@ def exs_upload_ligands(batch, pocket_ids=None, stream=None) -> int:
     if pocket_ids is not None:
         pk = np.asarray(pocket_ids, dtype=np.int64)[pk]
     pk = arr(pk, np.int32)
+    keep = (ao, x, y, z, ty, bo, bij, ro, rb, pk)
     s = exs_ligand_batch(int(ao.shape[0] - 1), _p(ao), _p(x), _p(y), _p(z), _p(ty), _p(bo),
                          _p(bij), _p(ro), _p(rb), _p(pk))
+    return s, keep
+
+
+def exs_upload_ligands(batch, pocket_ids=None, stream=None) -> int:
+    """batch: CSR arrays (attributes atom_offset, x, y, z, type, bond_offset, bond_ij,
+    rot_offset, rot_bond, pocket_id).  pocket_ids, if given, maps batch.pocket_id values
+    (pocket indices) to loaded pocket handles."""
+    s, keep = _batch_struct(batch, pocket_ids)
     out = C.c_int64()
     _check(lib().exs_upload_ligands(C.byref(s), _stream(stream), C.byref(out)))
     return out.value
@@ -222,3 +249,46 @@ def exs_job_elapsed_ms(job: int) -> float:
 
 def exs_release_job(job: int):
     _check(lib().exs_release_job(int(job)))
+
+
+def exs_server_create(pocket_ids, params: exs_search_params, hbm_budget_bytes: int = 0,
+                      max_iter_ligands: int = 0, max_inflight_iters: int = 0,
+                      max_arena_ligands: int = 0) -> int:
+    pk = np.ascontiguousarray(pocket_ids, dtype=np.int32)
+    cfg = exs_server_config(int(hbm_budget_bytes), int(max_iter_ligands), int(max_inflight_iters),
+                            int(max_arena_ligands), 0)
+    out = C.c_int64()
+    _check(lib().exs_server_create(_p(pk), int(pk.size), C.byref(params), C.byref(cfg),
+                                   C.byref(out)))
+    return out.value
+
+
+def exs_server_submit(server: int, batch, pocket_ids=None) -> int:
+    s, keep = _batch_struct(batch, pocket_ids)
+    out = C.c_int64()
+    _check(lib().exs_server_submit(int(server), C.byref(s), C.byref(out)))
+    return out.value
+
+
+def exs_server_poll(server: int, request: int, n_ligands: int, n_atoms: int, wait: bool = True):
+    """Returns None while the request is queued or running (wait=False), else a dict."""
+    best = np.zeros(n_ligands, np.float32)
+    desc = np.zeros(n_ligands, POSE_DESC)
+    xyz = np.zeros((n_atoms, 3), np.float32)
+    lat = C.c_double()
+    rc = lib().exs_server_poll(int(server), int(request), 1 if wait else 0, _p(best), _p(desc),
+                               _p(xyz), C.byref(lat))
+    if rc == EXS_ENOTREADY:
+        return None
+    _check(rc)
+    return dict(best_score=best, desc=desc, coords=xyz, latency_ms=lat.value)
+
+
+def exs_server_get_stats(server: int) -> dict:
+    st = exs_server_stats()
+    _check(lib().exs_server_get_stats(int(server), C.byref(st)))
+    return {name: getattr(st, name) for name, _ in exs_server_stats._fields_}
+
+
+def exs_server_destroy(server: int):
+    _check(lib().exs_server_destroy(int(server)))

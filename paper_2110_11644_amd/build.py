@@ -24,6 +24,7 @@ SOURCES = [
     ("dock_f16.hip", True),
     ("dock_misc.hip", True),
     ("exs_api.cpp", False),
+    ("exs_serve.cpp", False),
     ("exs_pack.cpp", False),
 ]
 HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]

@@ -23,6 +23,7 @@
 #include "exs.h"
 #include "exs_internal.h"
 #include "exs_pack.h"
+#include "exs_runtime.h"
 
 using namespace exs;
 
@@ -128,6 +129,16 @@ struct Pocket {
     std::atomic<int> users{0};
 };
 
+// A reusable execution plan of one (batch, settings) pair: device buffers that
+// outlive jobs and the launch sequence captured once in a hipGraph.
+struct Plan {
+    std::vector<void*> bufs;
+    DockArgs args{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::atomic<bool> busy{false};
+};
+
 struct Batch {
     int device = 0;
     int L = 0, A = 0, R = 0, n_max = 1;
@@ -146,6 +157,7 @@ struct Batch {
     std::mutex order_mu;
     std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
     std::map<std::vector<int>, std::vector<int>> group_sizes;
+    std::map<std::vector<int64_t>, std::shared_ptr<Plan>> plans;   // graph plans by settings
 };
 
 struct Job {
@@ -155,7 +167,8 @@ struct Job {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int L = 0, A = 0, R = 0, K = 0, top_k = 0;
-    std::vector<void*> bufs;    // stream-ordered allocations
+    std::vector<void*> bufs;    // stream-ordered allocations (eager jobs)
+    std::shared_ptr<Plan> plan; // graph jobs: buffers belong to the plan
     DockArgs args{};
 };
 
@@ -196,9 +209,55 @@ void free_batch(Batch* b) {
     for (void* p : ptrs) if (p) (void)hipFree(p);
     for (auto& kv : b->d_orders) (void)hipFree(kv.second);
     b->d_orders.clear();
+    for (auto& kv : b->plans) {
+        Plan& pl = *kv.second;
+        if (pl.exec) (void)hipGraphExecDestroy(pl.exec);
+        if (pl.graph) (void)hipGraphDestroy(pl.graph);
+        for (void* q : pl.bufs) (void)hipFree(q);
+    }
+    b->plans.clear();
 }
 
 }  // namespace
+
+namespace exs {
+namespace rt {
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+int current_device(int* dev) { return ::current_device(dev); }
+int ensure_device(int dev) { return ::ensure_device(dev); }
+int orientation_tables(int dev, int K, const float** r32, const double** r64) {
+    return ::orientation_tables(dev, K, r32, r64);
+}
+int device_cus(int dev) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return g_dev[dev].cus;
+}
+bool pocket_info(int32_t id, PocketInfo* out) {
+    auto p = find_pocket(id);
+    if (!p) return false;
+    out->device = p->device;
+    out->channels = p->channels;
+    out->storage = p->storage;
+    out->desc = p->desc;
+    return true;
+}
+void pocket_use(int32_t id, int delta) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    auto it = g_pockets.find(id);
+    if (it != g_pockets.end()) it->second->users += delta;
+}
+
+}  // namespace rt
+}  // namespace exs
 
 // ---- C ABI -------------------------------------------------------------------------------------
 
@@ -515,19 +574,37 @@ int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_
     return EXS_OK;
 }
 
+// Device buffers of a job: stream-ordered per job (eager), or plain and owned by
+// a graph plan (kept across jobs).
+struct Alloc {
+    std::vector<void*>* bufs;
+    hipStream_t stream;
+    bool stream_ordered;
+};
+
 template <class T>
-int job_alloc(Job& j, T** p, size_t count, hipStream_t st) {
+int job_alloc(Alloc& al, T** p, size_t count) {
     size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
     void* q = nullptr;
-    HIP_TRY(hipMallocAsync(&q, bytes, st));
-    j.bufs.push_back(q);
+    if (al.stream_ordered) HIP_TRY(hipMallocAsync(&q, bytes, al.stream));
+    else HIP_TRY(hipMalloc(&q, bytes));
+    al.bufs->push_back(q);
     *p = (T*)q;
     return EXS_OK;
+}
+
+void free_allocs(Alloc& al) {
+    for (void* p : *al.bufs) {
+        if (al.stream_ordered) (void)hipFreeAsync(p, al.stream);
+        else (void)hipFree(p);
+    }
+    al.bufs->clear();
 }
 
 void job_free(Job& j) {
     for (void* p : j.bufs) (void)hipFreeAsync(p, j.stream);
     j.bufs.clear();
+    if (j.plan) { j.plan->busy = false; j.plan.reset(); }
     if (j.ev0) (void)hipEventDestroy(j.ev0);
     if (j.ev1) (void)hipEventDestroy(j.ev1);
     j.ev0 = j.ev1 = nullptr;
@@ -566,6 +643,42 @@ void fill_desc(exs_pose_desc& d, float score, double s64, int k, int32_t tau_pac
     d.tau[2] = (int8_t)((tau_packed >> 16) & 0xff);
     d.n_rot = (uint8_t)nrot;
     for (int b = 0; b < nrot; ++b) d.theta[b] = theta[(size_t)b * theta_stride];
+}
+
+}  // namespace
+
+namespace {
+
+// The launch sequence of one job on `st`: a counter reset and one persistent dock
+// launch, or one dock launch per pocket group.
+hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<int>& groups,
+                        const int32_t* d_order, int storage, int ppl, bool persistent, int resident,
+                        int threads, size_t lds, hipStream_t st) {
+    if (b.L == 0) return hipSuccess;
+    if (persistent) {
+        DockArgs a = base;
+        a.order = d_order;
+        a.n_order = b.L;
+        a.n_tiles = (b.L + a.lpw - 1) / a.lpw;
+        a.persistent = 1;
+        hipError_t e = launch_zero_ints(a.tile_counter, 1, st);
+        if (e != hipSuccess) return e;
+        return launch_dock(a, storage, ppl, resident, threads, lds, st);
+    }
+    int start = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const int gsz = groups[gi];
+        if (gsz == 0) continue;
+        DockArgs a = base;
+        a.order = d_order + start;
+        a.n_order = gsz;
+        a.n_tiles = (gsz + a.lpw - 1) / a.lpw;
+        a.persistent = 0;
+        hipError_t e = launch_dock(a, b.storage_of_slot[gi], ppl, a.n_tiles, threads, lds, st);
+        if (e != hipSuccess) return e;
+        start += gsz;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -626,47 +739,15 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         auto j = std::make_shared<Job>();
         j->device = dev; j->batch = b; j->prm = p; j->stream = st;
         j->L = b->L; j->A = b->A; j->R = b->R; j->K = K; j->top_k = top_k;
-        DockArgs& a = j->args;
-        memset(&a, 0, sizeof a);
-        a.info = b->d_info; a.ref = b->d_ref; a.ref64 = b->d_ref64; a.excl = b->d_excl;
-        a.rot_uv = b->d_rot_uv; a.rot_mask = b->d_rot_mask; a.grids = b->d_grids;
-        a.rot32 = r32; a.rot64 = r64;
-        a.K = K; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
-        a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
-        a.step64 = (double)p.offset_step_A;
-        a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
-        a.pen64 = (double)p.clash_penalty;
-        a.top_k = top_k; a.lpw = lpw; a.wpl = wpl; a.kp = wpl * kWave * ppl;
-        a.n_max = b->n_max;
-        const int L = b->L, R = b->R, A = b->A;
-        int rc;
-        if ((rc = job_alloc(*j, &a.orient_score, (size_t)L * K, st)) ||
-            (rc = job_alloc(*j, &a.orient_theta, (size_t)R * K, st)) ||
-            (rc = job_alloc(*j, &a.orient_tau, (size_t)L * K, st)) ||
-            (rc = job_alloc(*j, &a.best_score, (size_t)L, st)) ||
-            (rc = job_alloc(*j, &a.best_k, (size_t)L, st)) ||
-            (rc = job_alloc(*j, &a.best_coords, (size_t)A * 3, st)) ||
-            (rc = job_alloc(*j, &a.best_theta, (size_t)R, st)) ||
-            (rc = job_alloc(*j, &a.best_tau, (size_t)L, st)) ||
-            (rc = job_alloc(*j, &a.best_score64, (size_t)L, st)) ||
-            (rc = job_alloc(*j, &a.topk_k, (size_t)L * top_k, st)) ||
-            (rc = job_alloc(*j, &a.topk_score, (size_t)L * top_k, st)) ||
-            (rc = job_alloc(*j, &a.topk_score64, (size_t)L * top_k, st)) ||
-            (rc = job_alloc(*j, &a.topk_theta, (size_t)R * top_k, st)) ||
-            (rc = job_alloc(*j, &a.topk_tau, (size_t)L * top_k, st)) ||
-            (rc = job_alloc(*j, &a.tile_counter, (size_t)1, st))) {
-            job_free(*j);
-            return rc;
-        }
-        a.slot_floats = (int64_t)lpw * a.n_max * 3 * a.kp;
+        const int L = b->L;
         const size_t lds = dock_lds_bytes(lpw, top_k);
-        const void* fn = dock_kernel_fn(storage < 0 ? 0 : storage, a.S, ppl);
-        if (!fn) { job_free(*j); return fail(EXS_EINVAL, "no kernel for this configuration"); }
+        const void* fn = dock_kernel_fn(storage < 0 ? 0 : storage, p.torsion_steps, ppl);
+        if (!fn) return fail(EXS_EINVAL, "no kernel for this configuration");
         if (lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) { job_free(*j); return fail(EXS_EDEVICE, "LDS %zu: %s", lds, hipGetErrorString(e)); }
+            if (e != hipSuccess) return fail(EXS_EDEVICE, "LDS %zu: %s", lds, hipGetErrorString(e));
         }
-        // scratch: one slot per workgroup (largest launch)
+        // workgroup slots of pose scratch: resident workgroups (persistent) or the largest launch
         int64_t slots = 0;
         int resident = 0;
         if (persistent) {
@@ -684,35 +765,102 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         } else {
             for (int gsz : groups) slots = std::max<int64_t>(slots, (gsz + lpw - 1) / lpw);
         }
-        if ((rc = job_alloc(*j, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats, st))) {
-            job_free(*j);
-            return rc;
+        const bool graph = (p.flags & EXS_FLAG_GRAPH) != 0;
+        std::shared_ptr<Plan> plan;
+        std::vector<int64_t> plan_key;
+        if (graph) {
+            plan_key = {K, p.torsion_steps, p.passes, p.n_offsets, top_k, ppl, lpw, p.flags,
+                        (int64_t)__builtin_bit_cast(uint32_t, p.offset_step_A),
+                        (int64_t)__builtin_bit_cast(uint32_t, p.clash_cutoff_A),
+                        (int64_t)__builtin_bit_cast(uint32_t, p.clash_penalty)};
+            std::lock_guard<std::mutex> lk(b->order_mu);
+            auto it = b->plans.find(plan_key);
+            if (it != b->plans.end()) plan = it->second;
+            if (plan) {
+                bool expect = false;
+                if (!plan->busy.compare_exchange_strong(expect, true))
+                    return fail(EXS_EINVAL, "the graph plan of these settings is held by an unreleased job");
+            }
+        }
+        if (plan && plan->exec) {
+            j->plan = plan;
+            j->args = plan->args;
+        } else {
+            DockArgs& a = j->args;
+            memset(&a, 0, sizeof a);
+            a.info = b->d_info; a.ref = b->d_ref; a.ref64 = b->d_ref64; a.excl = b->d_excl;
+            a.rot_uv = b->d_rot_uv; a.rot_mask = b->d_rot_mask; a.grids = b->d_grids;
+            a.rot32 = r32; a.rot64 = r64;
+            a.K = K; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
+            a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
+            a.step64 = (double)p.offset_step_A;
+            a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
+            a.pen64 = (double)p.clash_penalty;
+            a.top_k = top_k; a.lpw = lpw; a.wpl = wpl; a.kp = wpl * kWave * ppl;
+            a.n_max = b->n_max;
+            a.slot_floats = (int64_t)lpw * a.n_max * 3 * a.kp;
+            std::shared_ptr<Plan> fresh;
+            if (graph) fresh = std::make_shared<Plan>();
+            Alloc al{graph ? &fresh->bufs : &j->bufs, st, !graph};
+            const int R = b->R, A = b->A;
+            int rc;
+            if ((rc = job_alloc(al, &a.orient_score, (size_t)L * K)) ||
+                (rc = job_alloc(al, &a.orient_theta, (size_t)R * K)) ||
+                (rc = job_alloc(al, &a.orient_tau, (size_t)L * K)) ||
+                (rc = job_alloc(al, &a.best_score, (size_t)L)) ||
+                (rc = job_alloc(al, &a.best_k, (size_t)L)) ||
+                (rc = job_alloc(al, &a.best_coords, (size_t)A * 3)) ||
+                (rc = job_alloc(al, &a.best_theta, (size_t)R)) ||
+                (rc = job_alloc(al, &a.best_tau, (size_t)L)) ||
+                (rc = job_alloc(al, &a.best_score64, (size_t)L)) ||
+                (rc = job_alloc(al, &a.topk_k, (size_t)L * top_k)) ||
+                (rc = job_alloc(al, &a.topk_score, (size_t)L * top_k)) ||
+                (rc = job_alloc(al, &a.topk_score64, (size_t)L * top_k)) ||
+                (rc = job_alloc(al, &a.topk_theta, (size_t)R * top_k)) ||
+                (rc = job_alloc(al, &a.topk_tau, (size_t)L * top_k)) ||
+                (rc = job_alloc(al, &a.tile_counter, (size_t)1)) ||
+                (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
+                free_allocs(al);
+                return rc;
+            }
+            if (graph) {
+                fresh->args = a;
+                // capture the launch sequence once on a private stream
+                hipStream_t cs = nullptr;
+                HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    e = enqueue_dock(a, *b, groups, d_order, storage, ppl, persistent, resident,
+                                     threads, lds, cs);
+                    hipGraph_t gr = nullptr;
+                    hipError_t e2 = hipStreamEndCapture(cs, &gr);
+                    if (e == hipSuccess) e = e2;
+                    fresh->graph = gr;
+                    if (e == hipSuccess) e = hipGraphInstantiate(&fresh->exec, gr, nullptr, nullptr, 0);
+                }
+                (void)hipStreamDestroy(cs);
+                if (e != hipSuccess) {
+                    if (fresh->exec) (void)hipGraphExecDestroy(fresh->exec);
+                    if (fresh->graph) (void)hipGraphDestroy(fresh->graph);
+                    free_allocs(al);
+                    return fail(EXS_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+                }
+                fresh->busy = true;
+                {
+                    std::lock_guard<std::mutex> lk(b->order_mu);
+                    b->plans[plan_key] = fresh;
+                }
+                j->plan = fresh;
+            }
         }
         HIP_TRY(hipEventCreate(&j->ev0));
         HIP_TRY(hipEventCreate(&j->ev1));
         HIP_TRY(hipEventRecord(j->ev0, st));
-        if (L > 0) {
-            if (persistent) {
-                a.order = d_order;
-                a.n_order = L;
-                a.n_tiles = (L + lpw - 1) / lpw;
-                a.persistent = 1;
-                HIP_TRY(launch_zero_ints(a.tile_counter, 1, st));
-                HIP_TRY(launch_dock(a, storage, ppl, resident, threads, lds, st));
-            } else {
-                int start = 0;
-                for (size_t gi = 0; gi < groups.size(); ++gi) {
-                    const int gsz = groups[gi];
-                    if (gsz == 0) continue;
-                    DockArgs ga = a;
-                    ga.order = d_order + start;
-                    ga.n_order = gsz;
-                    ga.n_tiles = (gsz + lpw - 1) / lpw;
-                    ga.persistent = 0;
-                    HIP_TRY(launch_dock(ga, b->storage_of_slot[gi], ppl, ga.n_tiles, threads, lds, st));
-                    start += gsz;
-                }
-            }
+        if (j->plan) {
+            HIP_TRY(hipGraphLaunch(j->plan->exec, st));
+        } else {
+            HIP_TRY(enqueue_dock(j->args, *b, groups, d_order, storage, ppl, persistent, resident,
+                                 threads, lds, st));
         }
         HIP_TRY(hipEventRecord(j->ev1, st));
         std::lock_guard<std::mutex> lk(g_reg_mu);

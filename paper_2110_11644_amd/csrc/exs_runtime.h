@@ -1,0 +1,25 @@
+// Runtime services shared by the C ABI translation units (exs_api.cpp, exs_serve.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include "exs_internal.h"
+
+namespace exs {
+namespace rt {
+
+int fail(int code, const char* fmt, ...);                 // sets the thread's last error
+int current_device(int* dev);
+int ensure_device(int dev);                               // once per device: tables, pool
+int orientation_tables(int dev, int K, const float** r32, const double** r64);
+int device_cus(int dev);
+
+struct PocketInfo {
+    int device = 0, channels = 0, storage = 0;
+    GridDesc desc{};
+};
+bool pocket_info(int32_t id, PocketInfo* out);
+void pocket_use(int32_t id, int delta);                   // pin / unpin against unload
+
+}  // namespace rt
+}  // namespace exs

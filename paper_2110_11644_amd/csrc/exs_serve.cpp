@@ -1,0 +1,681 @@
+// Serving engine: continuous batching of docking requests on one GPU.
+//
+// The paper's docking application is a pipeline of stages with queues, whose
+// docker stage runs several workers per GPU to hide host-side preparation
+// (Sec. 3.2, 4.3).  Here one scheduler thread per server plays that role:
+//  * requests (a CSR ligand batch against resident pockets) are validated and
+//    packed on the submitting thread and queued;
+//  * admission: a request enters the device arena (ligand, atom and bond
+//    ranges, sized from the HBM budget) when its ranges fit -- FIFO, so a
+//    request that does not fit holds back the ones behind it (backpressure);
+//    its packed data is uploaded on an upload stream;
+//  * iterations: each launch is the persistent dock kernel over a work list of
+//    not-yet-docked ligands of the in-flight requests (oldest request first,
+//    longest ligand first within the list, capped per iteration); up to two
+//    iterations run at once on two streams, so a new iteration fills the CUs
+//    the previous one's tail leaves idle;
+//  * completion: a request whose last ligand finished has its results copied
+//    to host buffers and its arena ranges freed.
+// A ligand's result does not depend on what it is batched with (every lane
+// searches its own orientation; tiles hold whole ligands), so a request gives
+// the same answer alone and in the mix.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "exs.h"
+#include "exs_internal.h"
+#include "exs_pack.h"
+#include "exs_runtime.h"
+
+using namespace exs;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+#define SRV_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return rt::fail(e_ == hipErrorOutOfMemory ? EXS_ENOMEM : EXS_EDEVICE, "%s: %s", #expr, \
+                            hipGetErrorString(e_));                                        \
+    } while (0)
+
+// First-fit allocator of index ranges [0, cap).
+class RangeAlloc {
+  public:
+    void reset(int cap) { free_.clear(); if (cap > 0) free_[0] = cap; cap_ = cap; }
+    bool alloc(int n, int* start) {
+        if (n == 0) { *start = 0; return true; }
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *start = it->first;
+                int rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest > 0) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(int start, int n) {
+        if (n == 0) return;
+        auto it = free_.emplace(start, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int cap() const { return cap_; }
+
+  private:
+    std::map<int, int> free_;
+    int cap_ = 0;
+};
+
+enum ReqState { kQueued, kInflight, kDone };
+
+struct Request {
+    int64_t id = 0;
+    int L = 0, A = 0, R = 0;
+    // packed host data (request-local bases)
+    std::vector<LigInfo> info;
+    std::vector<float4> ref;
+    std::vector<double> ref64;
+    std::vector<uint4> excl;
+    std::vector<uint32_t> ruv;
+    std::vector<uint4> rmask;
+    std::vector<double> cost;
+    // arena ranges
+    int lig0 = 0, atom0 = 0, rot0 = 0;
+    int scheduled = 0, remaining = 0;
+    ReqState state = kQueued;
+    Clock::time_point t_submit, t_done;
+    // results
+    std::vector<float> best_score;
+    std::vector<exs_pose_desc> desc;
+    std::vector<float> coords;
+};
+
+struct Iteration {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    int32_t* d_order = nullptr;
+    int32_t* h_order = nullptr;   // pinned
+    int* d_counter = nullptr;
+    float* scratch = nullptr;
+    bool running = false;
+    std::vector<std::pair<Request*, int>> work;   // (request, ligands scheduled)
+    Clock::time_point t_launch;
+};
+
+class Server {
+  public:
+    ~Server() { shutdown(); }
+
+    int create(const int32_t* pockets, int n_pockets, const exs_search_params& p,
+               const exs_server_config& cfg);
+    int submit(const exs_ligand_batch& in, int64_t* id_out);
+    int poll(int64_t id, int wait, float* best_score, exs_pose_desc* desc, float* coords,
+             double* latency_ms);
+    void stats(exs_server_stats* out);
+    void shutdown();
+
+  private:
+    void loop();
+    bool admit_locked();
+    void complete(Iteration& it);
+    bool launch(Iteration& it);
+
+    int dev_ = 0;
+    exs_search_params prm_{};
+    int K_ = 0, ppl_ = 1, lpw_ = 1, wpl_ = 1, threads_ = 64, top_k_ = 0, storage_ = 0;
+    int resident_ = 1, max_iter_ = 0, n_iters_ = 2;
+    size_t lds_ = 0;
+    std::vector<int32_t> pocket_ids_;
+    std::unordered_map<int32_t, int> pocket_slot_;
+    std::vector<int> channels_;
+    DockArgs base_{};
+    std::vector<void*> dev_bufs_;
+    RangeAlloc lig_alloc_, atom_alloc_, rot_alloc_;
+    hipStream_t up_stream_ = nullptr, copy_stream_ = nullptr;
+    hipEvent_t up_event_ = nullptr;
+    bool up_pending_ = false;
+    Iteration it_[2];
+
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Request*> queue_;
+    std::vector<Request*> inflight_;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> reqs_;
+    int64_t next_id_ = 1;
+    bool stop_ = false;
+    std::thread thread_;
+    // stats
+    int64_t submitted_ = 0, completed_ = 0, iterations_ = 0, ligands_ = 0;
+    double busy_ms_ = 0.0;
+    std::string thread_error_;
+};
+
+template <class T>
+int dev_alloc(std::vector<void*>& bufs, T** p, size_t count) {
+    void* q = nullptr;
+    SRV_TRY(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+    bufs.push_back(q);
+    *p = (T*)q;
+    return EXS_OK;
+}
+
+int Server::create(const int32_t* pockets, int n_pockets, const exs_search_params& p,
+                   const exs_server_config& cfg) {
+    if (n_pockets < 1 || !pockets) return rt::fail(EXS_EINVAL, "a server needs at least one pocket");
+    if (int rc = rt::current_device(&dev_)) return rc;
+    if (int rc = rt::ensure_device(dev_)) return rc;
+    prm_ = p;
+    K_ = p.n_orient;
+    if (K_ < 1 || K_ > EXS_MAX_ORIENT) return rt::fail(EXS_EINVAL, "n_orient %d", K_);
+    if (p.torsion_steps != 8 && p.torsion_steps != 16 && p.torsion_steps != 32)
+        return rt::fail(EXS_EINVAL, "torsion_steps %d: supported 8, 16, 32", p.torsion_steps);
+    if (p.n_offsets != 1 && p.n_offsets != 27) return rt::fail(EXS_EINVAL, "n_offsets must be 1 or 27");
+    if (p.passes < 0 || p.passes > 64) return rt::fail(EXS_EINVAL, "passes %d", p.passes);
+    if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return rt::fail(EXS_EINVAL, "top_k %d", p.top_k);
+    ppl_ = p.poses_per_lane ? p.poses_per_lane : 1;
+    if (ppl_ != 1 && ppl_ != 2) return rt::fail(EXS_EINVAL, "poses_per_lane %d", ppl_);
+    wpl_ = (K_ + kWave * ppl_ - 1) / (kWave * ppl_);
+    lpw_ = p.ligands_per_wg ? p.ligands_per_wg : 1;
+    if ((lpw_ != 1 && lpw_ != 2 && lpw_ != 4 && lpw_ != 8) || lpw_ * wpl_ * kWave > kMaxThreadsPerWg)
+        return rt::fail(EXS_EINVAL, "ligands_per_wg %d does not fit a workgroup", lpw_);
+    threads_ = lpw_ * wpl_ * kWave;
+    top_k_ = std::min(p.top_k, K_);
+    lds_ = dock_lds_bytes(lpw_, top_k_);
+    n_iters_ = cfg.max_inflight_iters == 1 ? 1 : 2;
+    // pockets
+    std::vector<GridDesc> grids;
+    for (int i = 0; i < n_pockets; ++i) {
+        rt::PocketInfo pi;
+        if (!rt::pocket_info(pockets[i], &pi)) return rt::fail(EXS_EINVAL, "unknown pocket %d", pockets[i]);
+        if (pi.device != dev_) return rt::fail(EXS_EINVAL, "pocket %d is on another device", pockets[i]);
+        if (i > 0 && pi.storage != storage_)
+            return rt::fail(EXS_EINVAL, "all pockets of a server need the same texel storage");
+        storage_ = pi.storage;
+        pocket_slot_[pockets[i]] = i;
+        channels_.push_back(pi.channels);
+        grids.push_back(pi.desc);
+    }
+    const void* fn = dock_kernel_fn(storage_, p.torsion_steps, ppl_);
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_, lds_) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    resident_ = std::max(1, per_cu * rt::device_cus(dev_));
+    max_iter_ = cfg.max_iter_ligands > 0 ? cfg.max_iter_ligands : 2 * resident_ * lpw_;
+    // budget: scratch for the iterations first, the rest is the request arena
+    const int64_t slot_floats = (int64_t)lpw_ * EXS_MAX_ATOMS * 3 * (wpl_ * kWave * ppl_);
+    const int64_t scratch_bytes = (int64_t)n_iters_ * resident_ * slot_floats * 4;
+    const int64_t per_lig = 32 + 12LL * K_ + 40 + 28LL * top_k_ + 4;   // info, per-orientation, best, top-k, order
+    const int64_t per_atom = 16 + 24 + 16 + 12;
+    const int64_t per_rot = 4 + 16 + K_ + 1 + top_k_;
+    const int64_t unit = per_lig + 48 * per_atom + 16 * per_rot;      // 48 atoms, 16 bonds per ligand slot
+    const int64_t budget = cfg.hbm_budget_bytes > 0 ? cfg.hbm_budget_bytes : (int64_t)2 << 30;
+    const int64_t cap_l = (budget - scratch_bytes) / unit;
+    if (cap_l < 1) return rt::fail(EXS_ENOMEM, "HBM budget %lld below the iteration scratch (%lld)",
+                                   (long long)budget, (long long)scratch_bytes);
+    int64_t cap = std::min<int64_t>(cap_l, 1 << 24);
+    if (cfg.max_arena_ligands > 0) cap = std::min<int64_t>(cap, cfg.max_arena_ligands);
+    const int capL = (int)cap;
+    const int capA = capL * 48, capR = capL * 16;
+    lig_alloc_.reset(capL);
+    atom_alloc_.reset(capA);
+    rot_alloc_.reset(capR);
+    // arena
+    DockArgs& a = base_;
+    memset(&a, 0, sizeof a);
+    LigInfo* info;
+    float4* ref;
+    double* ref64;
+    uint4 *excl, *rmask;
+    uint32_t* ruv;
+    GridDesc* dg;
+    int rc;
+    if ((rc = dev_alloc(dev_bufs_, &info, capL)) || (rc = dev_alloc(dev_bufs_, &ref, capA)) ||
+        (rc = dev_alloc(dev_bufs_, &ref64, (size_t)capA * 3)) || (rc = dev_alloc(dev_bufs_, &excl, capA)) ||
+        (rc = dev_alloc(dev_bufs_, &ruv, capR)) || (rc = dev_alloc(dev_bufs_, &rmask, capR)) ||
+        (rc = dev_alloc(dev_bufs_, &dg, grids.size())) ||
+        (rc = dev_alloc(dev_bufs_, &a.orient_score, (size_t)capL * K_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.orient_theta, (size_t)capR * K_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.orient_tau, (size_t)capL * K_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.best_score, capL)) || (rc = dev_alloc(dev_bufs_, &a.best_k, capL)) ||
+        (rc = dev_alloc(dev_bufs_, &a.best_coords, (size_t)capA * 3)) ||
+        (rc = dev_alloc(dev_bufs_, &a.best_theta, capR)) || (rc = dev_alloc(dev_bufs_, &a.best_tau, capL)) ||
+        (rc = dev_alloc(dev_bufs_, &a.best_score64, capL)) ||
+        (rc = dev_alloc(dev_bufs_, &a.topk_k, (size_t)capL * top_k_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.topk_score, (size_t)capL * top_k_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.topk_score64, (size_t)capL * top_k_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.topk_theta, (size_t)capR * top_k_)) ||
+        (rc = dev_alloc(dev_bufs_, &a.topk_tau, (size_t)capL * top_k_)))
+        return rc;
+    SRV_TRY(hipMemcpy(dg, grids.data(), grids.size() * sizeof(GridDesc), hipMemcpyHostToDevice));
+    a.info = info; a.ref = ref; a.ref64 = ref64; a.excl = excl; a.rot_uv = ruv; a.rot_mask = rmask;
+    a.grids = dg;
+    if ((rc = rt::orientation_tables(dev_, K_, &a.rot32, &a.rot64))) return rc;
+    a.K = K_; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
+    a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
+    a.step64 = p.offset_step_A; a.cut2_64 = (double)p.clash_cutoff_A * p.clash_cutoff_A;
+    a.pen64 = p.clash_penalty;
+    a.top_k = top_k_; a.lpw = lpw_; a.wpl = wpl_; a.kp = wpl_ * kWave * ppl_;
+    a.n_max = EXS_MAX_ATOMS;
+    a.slot_floats = slot_floats;
+    a.persistent = 1;
+    SRV_TRY(hipStreamCreateWithFlags(&up_stream_, hipStreamNonBlocking));
+    SRV_TRY(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking));
+    SRV_TRY(hipEventCreateWithFlags(&up_event_, hipEventDisableTiming));
+    for (int i = 0; i < n_iters_; ++i) {
+        Iteration& it = it_[i];
+        SRV_TRY(hipStreamCreateWithFlags(&it.stream, hipStreamNonBlocking));
+        SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
+        if ((rc = dev_alloc(dev_bufs_, &it.d_order, max_iter_)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_counter, 1)) ||
+            (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)))
+            return rc;
+        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * max_iter_, hipHostMallocDefault));
+    }
+    pocket_ids_.assign(pockets, pockets + n_pockets);
+    for (int32_t id : pocket_ids_) rt::pocket_use(id, +1);
+    thread_ = std::thread([this] { loop(); });
+    return EXS_OK;
+}
+
+int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
+    const int L = in.n_ligands;
+    if (L < 1) return rt::fail(EXS_EINVAL, "empty request");
+    if (!in.atom_offset || !in.x || !in.y || !in.z || !in.type || !in.bond_offset ||
+        !in.rot_offset || !in.pocket_id)
+        return rt::fail(EXS_EINVAL, "null array in request");
+    if (in.atom_offset[0] != 0 || in.bond_offset[0] != 0 || in.rot_offset[0] != 0)
+        return rt::fail(EXS_EINVAL, "offsets must start at 0");
+    auto r = std::make_unique<Request>();
+    r->L = L;
+    r->A = in.atom_offset[L];
+    r->R = in.rot_offset[L];
+    if (r->R > 0 && !in.rot_bond) return rt::fail(EXS_EINVAL, "null rot_bond");
+    if (in.bond_offset[L] > 0 && !in.bond_ij) return rt::fail(EXS_EINVAL, "null bond_ij");
+    if (r->L > lig_alloc_.cap() || r->A > atom_alloc_.cap() || r->R > rot_alloc_.cap())
+        return rt::fail(EXS_ENOMEM, "request of %d ligands / %d atoms exceeds the server arena", L, r->A);
+    r->info.resize(L); r->ref.resize(r->A); r->ref64.resize((size_t)r->A * 3); r->excl.resize(r->A);
+    r->ruv.resize(r->R); r->rmask.resize(r->R); r->cost.resize(L);
+    for (int l = 0; l < L; ++l) {
+        if (in.atom_offset[l + 1] < in.atom_offset[l] || in.bond_offset[l + 1] < in.bond_offset[l] ||
+            in.rot_offset[l + 1] < in.rot_offset[l])
+            return rt::fail(EXS_EINVAL, "ligand %d: offsets decrease", l);
+        auto ps = pocket_slot_.find(in.pocket_id[l]);
+        if (ps == pocket_slot_.end())
+            return rt::fail(EXS_EINVAL, "ligand %d: pocket %d is not served", l, in.pocket_id[l]);
+        int a0 = in.atom_offset[l], n = in.atom_offset[l + 1] - a0;
+        int b0 = in.bond_offset[l], nb = in.bond_offset[l + 1] - b0;
+        int r0 = in.rot_offset[l], nr = in.rot_offset[l + 1] - r0;
+        PackedLigand pk;
+        std::string err;
+        int rc = pack_ligand(n, in.bond_ij + 2 * (size_t)b0, nb, in.rot_bond + r0, nr, in.type + a0,
+                             channels_[ps->second], in.x + a0, in.y + a0, in.z + a0, &pk, &err);
+        if (rc) return rt::fail(rc, "ligand %d: %s", l, err.c_str());
+        LigInfo& inf = r->info[l];
+        memset(&inf, 0, sizeof inf);
+        inf.atom_base = a0; inf.rot_base = r0; inf.n = (int16_t)n; inf.nrot = (int16_t)nr;
+        inf.pocket = (int16_t)ps->second;
+        std::vector<int16_t> m(nr);
+        for (int i = 0; i < n; ++i) {
+            double dx = (double)in.x[a0 + i] - pk.centroid[0], dy = (double)in.y[a0 + i] - pk.centroid[1],
+                   dz = (double)in.z[a0 + i] - pk.centroid[2];
+            r->ref[a0 + i] = make_float4((float)dx, (float)dy, (float)dz,
+                                         __builtin_bit_cast(float, (int)in.type[a0 + i]));
+            r->ref64[(size_t)(a0 + i) * 3] = dx;
+            r->ref64[(size_t)(a0 + i) * 3 + 1] = dy;
+            r->ref64[(size_t)(a0 + i) * 3 + 2] = dz;
+            r->excl[a0 + i] = pk.excl[i].as_uint4();
+        }
+        for (int b = 0; b < nr; ++b) {
+            r->ruv[r0 + b] = (uint32_t)pk.rot_u[b] | ((uint32_t)pk.rot_v[b] << 16);
+            r->rmask[r0 + b] = pk.moving[b].as_uint4();
+            m[b] = (int16_t)pk.moving[b].count();
+        }
+        r->cost[l] = ligand_cost(n, m.data(), nr, K_, prm_.torsion_steps, prm_.passes, prm_.n_offsets);
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    if (stop_) return rt::fail(EXS_EINVAL, "server is shutting down");
+    if (!thread_error_.empty()) return rt::fail(EXS_EDEVICE, "server failed: %s", thread_error_.c_str());
+    r->id = next_id_++;
+    r->remaining = L;
+    r->t_submit = Clock::now();
+    *id_out = r->id;
+    queue_.push_back(r.get());
+    reqs_[r->id] = std::move(r);
+    submitted_++;
+    cv_.notify_all();
+    return EXS_OK;
+}
+
+// Move queued requests into the arena while they fit (FIFO).  Called with mu_ held.
+bool Server::admit_locked() {
+    bool any = false;
+    while (!queue_.empty()) {
+        Request* r = queue_.front();
+        int l0, a0, r0;
+        if (!lig_alloc_.alloc(r->L, &l0)) break;
+        if (!atom_alloc_.alloc(r->A, &a0)) { lig_alloc_.release(l0, r->L); break; }
+        if (!rot_alloc_.alloc(r->R, &r0)) {
+            lig_alloc_.release(l0, r->L); atom_alloc_.release(a0, r->A); break;
+        }
+        queue_.pop_front();
+        r->lig0 = l0; r->atom0 = a0; r->rot0 = r0;
+        for (auto& inf : r->info) { inf.atom_base += a0; inf.rot_base += r0; }
+        const DockArgs& a = base_;
+        (void)hipMemcpyAsync((void*)(a.info + l0), r->info.data(), sizeof(LigInfo) * r->L, hipMemcpyHostToDevice, up_stream_);
+        if (r->A) {
+            (void)hipMemcpyAsync((void*)(a.ref + a0), r->ref.data(), sizeof(float4) * r->A, hipMemcpyHostToDevice, up_stream_);
+            (void)hipMemcpyAsync((void*)(a.ref64 + (size_t)a0 * 3), r->ref64.data(), sizeof(double) * 3 * r->A, hipMemcpyHostToDevice, up_stream_);
+            (void)hipMemcpyAsync((void*)(a.excl + a0), r->excl.data(), sizeof(uint4) * r->A, hipMemcpyHostToDevice, up_stream_);
+        }
+        if (r->R) {
+            (void)hipMemcpyAsync((void*)(a.rot_uv + r0), r->ruv.data(), sizeof(uint32_t) * r->R, hipMemcpyHostToDevice, up_stream_);
+            (void)hipMemcpyAsync((void*)(a.rot_mask + r0), r->rmask.data(), sizeof(uint4) * r->R, hipMemcpyHostToDevice, up_stream_);
+        }
+        r->state = kInflight;
+        inflight_.push_back(r);
+        any = true;
+    }
+    if (any) {
+        (void)hipEventRecord(up_event_, up_stream_);
+        up_pending_ = true;
+    }
+    return any;
+}
+
+bool Server::launch(Iteration& it) {
+    // oldest requests first, up to max_iter_ ligands
+    std::vector<std::pair<double, int32_t>> list;
+    it.work.clear();
+    for (Request* r : inflight_) {
+        if ((int)list.size() >= max_iter_) break;
+        int take = std::min(r->L - r->scheduled, max_iter_ - (int)list.size());
+        if (take <= 0) continue;
+        for (int i = 0; i < take; ++i)
+            list.emplace_back(r->cost[r->scheduled + i], r->lig0 + r->scheduled + i);
+        r->scheduled += take;
+        it.work.emplace_back(r, take);
+    }
+    if (list.empty()) return false;
+    std::stable_sort(list.begin(), list.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (size_t i = 0; i < list.size(); ++i) it.h_order[i] = list[i].second;
+    if (up_pending_) (void)hipStreamWaitEvent(it.stream, up_event_, 0);
+    DockArgs a = base_;
+    a.order = it.d_order;
+    a.n_order = (int)list.size();
+    a.n_tiles = (a.n_order + lpw_ - 1) / lpw_;
+    a.tile_counter = it.d_counter;
+    a.scratch = it.scratch;
+    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * list.size(),
+                                  hipMemcpyHostToDevice, it.stream);
+    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, 1, it.stream);
+    if (e == hipSuccess)
+        e = launch_dock(a, storage_, ppl_, std::min(resident_, a.n_tiles), threads_, lds_, it.stream);
+    if (e == hipSuccess) e = hipEventRecord(it.done, it.stream);
+    if (e != hipSuccess) {
+        thread_error_ = hipGetErrorString(e);
+        return false;
+    }
+    it.running = true;
+    it.t_launch = Clock::now();
+    iterations_++;
+    return true;
+}
+
+void Server::complete(Iteration& it) {
+    it.running = false;
+    busy_ms_ += std::chrono::duration<double, std::milli>(Clock::now() - it.t_launch).count();
+    for (auto& w : it.work) {
+        Request* r = w.first;
+        r->remaining -= w.second;
+        ligands_ += w.second;
+        if (r->remaining > 0) continue;
+        // copy the results out, then free the arena ranges
+        const DockArgs& a = base_;
+        std::vector<int32_t> bk(r->L), bt(r->L);
+        std::vector<uint8_t> th(r->R);
+        std::vector<double> b64(r->L, NAN);
+        r->best_score.resize(r->L);
+        r->coords.resize((size_t)r->A * 3);
+        (void)hipMemcpyAsync(r->best_score.data(), a.best_score + r->lig0, sizeof(float) * r->L, hipMemcpyDeviceToHost, copy_stream_);
+        (void)hipMemcpyAsync(bk.data(), a.best_k + r->lig0, sizeof(int32_t) * r->L, hipMemcpyDeviceToHost, copy_stream_);
+        (void)hipMemcpyAsync(bt.data(), a.best_tau + r->lig0, sizeof(int32_t) * r->L, hipMemcpyDeviceToHost, copy_stream_);
+        if (r->R) (void)hipMemcpyAsync(th.data(), a.best_theta + r->rot0, r->R, hipMemcpyDeviceToHost, copy_stream_);
+        if (top_k_ > 0) (void)hipMemcpyAsync(b64.data(), a.best_score64 + r->lig0, sizeof(double) * r->L, hipMemcpyDeviceToHost, copy_stream_);
+        if (r->A) (void)hipMemcpyAsync(r->coords.data(), a.best_coords + (size_t)r->atom0 * 3, sizeof(float) * 3 * r->A, hipMemcpyDeviceToHost, copy_stream_);
+        (void)hipStreamSynchronize(copy_stream_);
+        r->desc.resize(r->L);
+        for (int l = 0; l < r->L; ++l) {
+            exs_pose_desc& d = r->desc[l];
+            memset(&d, 0, sizeof d);
+            d.score = r->best_score[l];
+            d.score_fp64 = b64[l];
+            d.orient = bk[l];
+            d.tau[0] = (int8_t)(bt[l] & 0xff);
+            d.tau[1] = (int8_t)((bt[l] >> 8) & 0xff);
+            d.tau[2] = (int8_t)((bt[l] >> 16) & 0xff);
+            const LigInfo& inf = r->info[l];
+            d.n_rot = (uint8_t)inf.nrot;
+            for (int b = 0; b < inf.nrot; ++b) d.theta[b] = th[inf.rot_base - r->rot0 + b];
+        }
+        if (top_k_ > 0)
+            for (int l = 0; l < r->L; ++l) r->best_score[l] = (float)b64[l];
+        lig_alloc_.release(r->lig0, r->L);
+        atom_alloc_.release(r->atom0, r->A);
+        rot_alloc_.release(r->rot0, r->R);
+        r->state = kDone;
+        r->t_done = Clock::now();
+        completed_++;
+        inflight_.erase(std::find(inflight_.begin(), inflight_.end(), r));
+        // release the packed inputs
+        std::vector<float4>().swap(r->ref);
+        std::vector<double>().swap(r->ref64);
+        std::vector<uint4>().swap(r->excl);
+        std::vector<uint4>().swap(r->rmask);
+    }
+    it.work.clear();
+    done_cv_.notify_all();
+}
+
+void Server::loop() {
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+        bool progress = false;
+        if (thread_error_.empty()) {
+            if (admit_locked()) progress = true;
+            for (int i = 0; i < n_iters_; ++i) {
+                Iteration& it = it_[i];
+                if (it.running && hipEventQuery(it.done) == hipSuccess) {
+                    complete(it);
+                    progress = true;
+                }
+            }
+            if (admit_locked()) progress = true;
+            for (int i = 0; i < n_iters_; ++i)
+                if (!it_[i].running && launch(it_[i])) progress = true;
+        }
+        bool running = false;
+        for (int i = 0; i < n_iters_; ++i) running |= it_[i].running;
+        if (stop_ && !running) break;
+        if (!thread_error_.empty()) {
+            done_cv_.notify_all();
+            if (stop_) break;
+        }
+        if (!progress) {
+            if (running) cv_.wait_for(lk, std::chrono::microseconds(50));
+            else cv_.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+int Server::poll(int64_t id, int wait, float* best_score, exs_pose_desc* desc, float* coords,
+                 double* latency_ms) {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = reqs_.find(id);
+    if (it == reqs_.end()) return rt::fail(EXS_ENOENT, "unknown request %lld", (long long)id);
+    Request* r = it->second.get();
+    if (wait)
+        done_cv_.wait(lk, [&] { return r->state == kDone || !thread_error_.empty() || stop_; });
+    if (r->state != kDone) {
+        if (!thread_error_.empty()) return rt::fail(EXS_EDEVICE, "server failed: %s", thread_error_.c_str());
+        if (stop_) return rt::fail(EXS_EINVAL, "server shut down before request %lld finished", (long long)id);
+        return rt::fail(EXS_ENOTREADY, "request %lld is %s", (long long)id,
+                        r->state == kQueued ? "queued" : "running");
+    }
+    if (best_score) memcpy(best_score, r->best_score.data(), sizeof(float) * r->L);
+    if (desc) memcpy(desc, r->desc.data(), sizeof(exs_pose_desc) * r->L);
+    if (coords) memcpy(coords, r->coords.data(), sizeof(float) * 3 * r->A);
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    reqs_.erase(it);
+    return EXS_OK;
+}
+
+void Server::stats(exs_server_stats* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    memset(out, 0, sizeof *out);
+    out->submitted = submitted_;
+    out->completed = completed_;
+    out->queued = (int64_t)queue_.size();
+    out->inflight = (int64_t)inflight_.size();
+    out->iterations = iterations_;
+    out->ligands_docked = ligands_;
+    out->arena_ligands = lig_alloc_.cap();
+    out->arena_atoms = atom_alloc_.cap();
+    out->busy_ms = busy_ms_;
+}
+
+void Server::shutdown() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (stop_ && !thread_.joinable()) return;
+        stop_ = true;
+        queue_.clear();
+        cv_.notify_all();
+        done_cv_.notify_all();
+    }
+    if (thread_.joinable()) thread_.join();
+    for (int i = 0; i < 2; ++i) {
+        Iteration& it = it_[i];
+        if (it.stream) { (void)hipStreamSynchronize(it.stream); (void)hipStreamDestroy(it.stream); }
+        if (it.done) (void)hipEventDestroy(it.done);
+        if (it.h_order) (void)hipHostFree(it.h_order);
+        it = Iteration();
+    }
+    if (up_stream_) { (void)hipStreamSynchronize(up_stream_); (void)hipStreamDestroy(up_stream_); }
+    if (copy_stream_) (void)hipStreamDestroy(copy_stream_);
+    if (up_event_) (void)hipEventDestroy(up_event_);
+    up_stream_ = copy_stream_ = nullptr;
+    up_event_ = nullptr;
+    for (void* p : dev_bufs_) (void)hipFree(p);
+    dev_bufs_.clear();
+    for (int32_t id : pocket_ids_) rt::pocket_use(id, -1);
+    pocket_ids_.clear();
+}
+
+std::mutex g_srv_mu;
+std::unordered_map<int64_t, std::shared_ptr<Server>> g_servers;
+int64_t g_next_server = 1;
+
+std::shared_ptr<Server> find_server(int64_t id) {
+    std::lock_guard<std::mutex> lk(g_srv_mu);
+    auto it = g_servers.find(id);
+    return it == g_servers.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
+int exs_server_create(const int32_t* pocket_ids, int n_pockets, const exs_search_params* params,
+                      const exs_server_config* cfg, int64_t* server_out) {
+    try {
+        if (!params || !server_out) return rt::fail(EXS_EINVAL, "null argument");
+        exs_server_config c{};
+        if (cfg) c = *cfg;
+        auto s = std::make_shared<Server>();
+        if (int rc = s->create(pocket_ids, n_pockets, *params, c)) {
+            s->shutdown();
+            return rc;
+        }
+        std::lock_guard<std::mutex> lk(g_srv_mu);
+        int64_t id = g_next_server++;
+        g_servers[id] = s;
+        *server_out = id;
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return rt::fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_server_submit(int64_t server, const exs_ligand_batch* request, int64_t* request_out) {
+    try {
+        if (!request || !request_out) return rt::fail(EXS_EINVAL, "null argument");
+        auto s = find_server(server);
+        if (!s) return rt::fail(EXS_ENOENT, "unknown server %lld", (long long)server);
+        return s->submit(*request, request_out);
+    } catch (const std::exception& e) {
+        return rt::fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_server_poll(int64_t server, int64_t request, int wait, float* best_score,
+                    exs_pose_desc* desc, float* coords, double* latency_ms) {
+    try {
+        auto s = find_server(server);
+        if (!s) return rt::fail(EXS_ENOENT, "unknown server %lld", (long long)server);
+        return s->poll(request, wait, best_score, desc, coords, latency_ms);
+    } catch (const std::exception& e) {
+        return rt::fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_server_get_stats(int64_t server, exs_server_stats* out) {
+    if (!out) return rt::fail(EXS_EINVAL, "null argument");
+    auto s = find_server(server);
+    if (!s) return rt::fail(EXS_ENOENT, "unknown server %lld", (long long)server);
+    s->stats(out);
+    return EXS_OK;
+}
+
+int exs_server_destroy(int64_t server) {
+    std::shared_ptr<Server> s;
+    {
+        std::lock_guard<std::mutex> lk(g_srv_mu);
+        auto it = g_servers.find(server);
+        if (it == g_servers.end()) return rt::fail(EXS_ENOENT, "unknown server %lld", (long long)server);
+        s = it->second;
+        g_servers.erase(it);
+    }
+    s->shutdown();
+    return EXS_OK;
+}
+
+}  // extern "C"

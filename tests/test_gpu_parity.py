@@ -220,3 +220,88 @@ def test_invalid_requests_fail_alone(B, small):
         B.exs_release_ligands(bid)
     finally:
         B.exs_unload_pocket(pid)
+
+
+@pytest.mark.parametrize("storage,rounder", [(1, S.to_bf16_rne), (2, S.to_f16_rne)],
+                         ids=["bf16", "f16"])
+def test_16bit_texels_match_oracle_on_rounded_grid(B, oracle_lib, small, storage, rounder):
+    """BF16/FP16 storage with FP32 interpolation equals the FP32 path on the RNE-rounded grid:
+    the oracle, fed that rounded grid, is the reference (rounding done by numpy)."""
+    O = oracle_lib
+    p, _, batch = small
+    s = S.SMALL.search
+    sub = batch.subset(range(16))
+    log("16-bit storage %d" % storage)
+    out = run(B, [p], sub, s, storage=storage)
+    g16 = O.Grid(rounder(p.values), p.spacing, p.origin)
+    stats = check_all(O, [g16], O.Params.of(s), sub, out)
+    log("16-bit stats", stats)
+
+
+def test_fp64_rescoring_of_top_k(B, oracle_lib, small):
+    """top_k poses per ligand rescored in FP64 on the GPU equal the oracle's FP64 score of the
+    same descriptors; the final best is the FP64 argmin among them."""
+    O = oracle_lib
+    p, g, batch = small
+    s = S.SMALL.search
+    sub = batch.subset(range(12))
+    tk = 8
+    log("fp64 rescoring top_k=%d" % tk)
+    out = run(B, [p], sub, s, top_k=tk)
+    prm = O.Params.of(s)
+    for l in range(sub.n_ligands):
+        lig = sub.ligand(l)
+        top = out["topk"][l]
+        sc = out["score"][l]
+        order = sorted(range(s.n_orient), key=lambda k: (sc[k], k))[:tk]
+        assert [int(d["orient"]) for d in top] == order
+        e64 = []
+        for d in top:
+            e, _, amb = O.rescore_desc(g, prm, lig, int(d["orient"]), d["theta"][:len(lig.rot)],
+                                       d["tau"])[:3]
+            assert abs(float(d["score_fp64"]) - e) <= 1e-9 * max(1.0, abs(e)) + prm.clash_penalty * amb
+            assert float(d["score"]) == float(sc[int(d["orient"])])
+            e64.append(float(d["score_fp64"]))
+        j = int(np.argmin(e64))
+        assert int(out["best"][l]["orient"]) == int(top[j]["orient"])
+        assert float(out["best"][l]["score_fp64"]) == e64[j]
+        assert float(out["best_score"][l]) == np.float32(e64[j])
+        a0, a1 = int(sub.atom_offset[l]), int(sub.atom_offset[l + 1])
+        X = O.pose_from_desc(g, prm, lig, int(top[j]["orient"]), top[j]["theta"][:len(lig.rot)],
+                             top[j]["tau"])
+        assert np.max(np.abs(out["coords"][a0:a1] - X)) < 1e-5
+
+
+def test_graph_replays_match_eager(B, small):
+    """EXS_FLAG_GRAPH: the captured launch sequence (counter reset + persistent dock kernel)
+    replayed several times, with eager jobs and synchronisations in between, equals the eager
+    result every time."""
+    p, g, batch = small
+    s = S.SMALL.search
+    eager = run(B, [p], batch, s, flags=B.EXS_FLAG_PERSISTENT, lpw=2)
+    pid = B.exs_load_pocket_grid(p.values, p.spacing, p.origin)
+    bid = B.exs_upload_ligands(batch, pocket_ids=[pid])
+    L, A = batch.n_ligands, int(batch.atom_offset[-1])
+    gp = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, ligands_per_wg=2,
+                         flags=B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH)
+    ep = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, ligands_per_wg=1)
+    try:
+        for rep in range(3):
+            log("graph replay", rep)
+            job = B.exs_dock_batch(bid, gp)
+            with pytest.raises(B.ExsError):
+                B.exs_dock_batch(bid, gp)              # plan held by the unreleased job
+            out = B.exs_get_best_poses(job, L, A)
+            orient = B.exs_get_orientation_results(job, L, s.n_orient)
+            B.exs_release_job(job)
+            assert np.array_equal(out["best_score"], eager["best_score"])
+            assert np.array_equal(out["coords"], eager["coords"])
+            assert np.array_equal(orient["score"], eager["score"])
+            assert np.array_equal(orient["desc"]["theta"], eager["desc"]["theta"])
+            # eager work and a sync between replays
+            job2 = B.exs_dock_batch(bid, ep)
+            B.exs_get_best_poses(job2, L, A)
+            B.exs_release_job(job2)
+    finally:
+        B.exs_release_ligands(bid)
+        B.exs_unload_pocket(pid)

@@ -1,0 +1,145 @@
+"""Serving (continuous batching) on the GPU through the C ABI: every request's
+result equals the result of docking its ligands alone; invalid requests fail
+alone; a small arena forces queueing (backpressure) without losing requests."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import exs_synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2110_11644_amd import binding
+    binding.lib()
+    return binding
+
+
+WL = S.Workload("serve-test", 92, 0, 3, (32, 40, 48), 0.375, 8, ("lognormal", 35.0, 0.4, 10, 90),
+                ("uniform", 0, 15), S.SearchSettings(64, 8, 1, 27))
+
+
+@pytest.fixture(scope="module")
+def setup(B):
+    pockets = [S.make_pocket(WL, i) for i in range(3)]
+    pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin) for p in pockets]
+    rng = np.random.default_rng(3)
+    reqs = []
+    start = 0
+    for r in range(12):
+        size = int(rng.integers(1, 24))
+        ligs = S.make_ligands(WL, start, size)
+        pk = int(rng.integers(0, 3))
+        for l in ligs:
+            l.pocket = pk
+        reqs.append(S.batch_from_ligands(ligs))
+        start += size
+    yield pids, reqs
+    for pid in pids:
+        B.exs_unload_pocket(pid)
+
+
+def params(B, s=WL.search):
+    return B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, ligands_per_wg=1)
+
+
+def alone(B, pids, batch):
+    bid = B.exs_upload_ligands(batch, pocket_ids=pids)
+    job = B.exs_dock_batch(bid, params(B))
+    out = B.exs_get_best_poses(job, batch.n_ligands, int(batch.atom_offset[-1]))
+    B.exs_release_job(job)
+    B.exs_release_ligands(bid)
+    return out
+
+
+def serve(B, pids, reqs, gap_s=0.0, **cfg):
+    srv = B.exs_server_create(pids, params(B), **cfg)
+    results = {}
+    try:
+        ids = []
+        for r in reqs:
+            ids.append(B.exs_server_submit(srv, r, pocket_ids=pids))
+            if gap_s:
+                time.sleep(gap_s)
+        for i, (rid, r) in enumerate(zip(ids, reqs)):
+            results[i] = B.exs_server_poll(srv, rid, r.n_ligands, int(r.atom_offset[-1]))
+        stats = B.exs_server_get_stats(srv)
+    finally:
+        B.exs_server_destroy(srv)
+    return results, stats
+
+
+def test_each_request_alone_equals_in_the_mix(B, setup):
+    pids, reqs = setup
+    log("serving: 12 requests, arrivals 2 ms apart")
+    res, stats = serve(B, pids, reqs, gap_s=0.002)
+    log("stats", stats)
+    assert stats["completed"] == len(reqs)
+    for i, r in enumerate(reqs):
+        a = alone(B, pids, r)
+        m = res[i]
+        assert np.array_equal(a["best_score"], m["best_score"]), i
+        assert np.array_equal(a["desc"]["orient"], m["desc"]["orient"]), i
+        assert np.array_equal(a["desc"]["theta"], m["desc"]["theta"]), i
+        assert np.array_equal(a["desc"]["tau"], m["desc"]["tau"]), i
+        assert np.array_equal(a["coords"], m["coords"]), i
+        assert m["latency_ms"] > 0
+
+
+def test_small_arena_queues_requests_without_losing_any(B, setup):
+    pids, reqs = setup
+    log("serving: arena of 24 ligands, max 16 ligands per launch, one launch in flight")
+    res, stats = serve(B, pids, reqs, max_arena_ligands=24, max_iter_ligands=16,
+                       max_inflight_iters=1)
+    log("stats", stats)
+    assert stats["arena_ligands"] == 24
+    assert stats["completed"] == len(reqs)
+    assert stats["iterations"] >= sum(r.n_ligands for r in reqs) // 16
+    ref, _ = serve(B, pids, reqs)
+    for i in range(len(reqs)):
+        assert np.array_equal(ref[i]["best_score"], res[i]["best_score"])
+
+
+def test_invalid_request_fails_alone(B, setup):
+    pids, reqs = setup
+    srv = B.exs_server_create(pids, params(B))
+    try:
+        good = B.exs_server_submit(srv, reqs[0], pocket_ids=pids)
+        bad = reqs[1].subset(range(reqs[1].n_ligands))
+        bad.type[0] = 9                                  # channel out of range
+        with pytest.raises(B.ExsError) as ei:
+            B.exs_server_submit(srv, bad, pocket_ids=pids)
+        assert ei.value.code == B.EXS_EINVAL
+        with pytest.raises(B.ExsError) as ei:            # pocket the server does not hold
+            B.exs_server_submit(srv, reqs[2], pocket_ids=[p + 100 for p in pids])
+        assert ei.value.code == B.EXS_EINVAL
+        good2 = B.exs_server_submit(srv, reqs[3], pocket_ids=pids)
+        for rid, r in ((good, reqs[0]), (good2, reqs[3])):
+            out = B.exs_server_poll(srv, rid, r.n_ligands, int(r.atom_offset[-1]))
+            assert np.all(np.isfinite(out["best_score"]))
+    finally:
+        B.exs_server_destroy(srv)
+
+
+def test_request_larger_than_the_arena_is_refused(B, setup):
+    pids, reqs = setup
+    srv = B.exs_server_create(pids, params(B), max_arena_ligands=4)
+    try:
+        big = max(reqs, key=lambda r: r.n_ligands)
+        with pytest.raises(B.ExsError) as ei:
+            B.exs_server_submit(srv, big, pocket_ids=pids)
+        assert ei.value.code == B.EXS_ENOMEM
+    finally:
+        B.exs_server_destroy(srv)
