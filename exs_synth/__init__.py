@@ -140,7 +140,52 @@ class Pocket:
 def pocket_grid_values(edge: int, spacing: float, pseudo_xyz: np.ndarray, pseudo_w: np.ndarray,
                        sigma: float = 1.2, core_radius: float = 1.2, core_value: float = 10.0
                        ) -> np.ndarray:
-    """Texel values of a synthetic pocket, FP64 -> RNE FP32, layout [C][z][y][x]."""
+    """Texel values of a synthetic pocket, FP64 -> RNE FP32, layout [C][z][y][x].
+
+    The Gaussian sum is evaluated separably (exp(-d^2/2s^2) is the product of the three
+    per-axis factors), as one small matrix product per z slice; the +core_value cores are
+    marked by exact distance tests in the box around each pseudo-atom."""
+    n = int(edge)
+    c = pseudo_w.shape[1]
+    origin = -spacing * (n - 1) / 2.0
+    axis = origin + spacing * np.arange(n, dtype=np.float64)
+    two_s2 = 2.0 * sigma * sigma
+    gx = np.exp(-(axis[None, :] - pseudo_xyz[:, 0:1]) ** 2 / two_s2)   # [300, n]
+    gy = np.exp(-(axis[None, :] - pseudo_xyz[:, 1:2]) ** 2 / two_s2)
+    gz = np.exp(-(axis[None, :] - pseudo_xyz[:, 2:3]) ** 2 / two_s2)
+    out = np.empty((c, n, n, n), dtype=np.float32)
+    wy = pseudo_w[:, :, None] * gy[:, None, :]                           # [300, C, n(y)]
+    wy = wy.transpose(1, 2, 0).reshape(c * n, -1)                        # [(C, y), 300]
+    for k in range(n):
+        m = gx * gz[:, k:k + 1]                                          # [300, n(x)]
+        out[:, k, :, :] = (wy @ m).reshape(c, n, n).astype(np.float32)
+    # cores: texels closer than core_radius to any pseudo-atom
+    core = np.zeros((n, n, n), dtype=bool)
+    reach = int(np.ceil(core_radius / spacing)) + 1
+    for a in range(pseudo_xyz.shape[0]):
+        ctr = np.round((pseudo_xyz[a] - origin) / spacing).astype(int)
+        lo = np.maximum(ctr - reach, 0)
+        hi = np.minimum(ctr + reach + 1, n)
+        if np.any(lo >= hi):
+            continue
+        zz, yy, xx = np.meshgrid(axis[lo[2]:hi[2]], axis[lo[1]:hi[1]], axis[lo[0]:hi[0]],
+                                 indexing="ij")
+        d = np.sqrt((xx - pseudo_xyz[a, 0]) ** 2 + (yy - pseudo_xyz[a, 1]) ** 2
+                    + (zz - pseudo_xyz[a, 2]) ** 2)
+        core[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= d < core_radius
+    if core.any():
+        idx = np.nonzero(core)
+        for ch in range(c):
+            # add in FP64 before rounding, as the definition states
+            vals = (wy.reshape(c, n, -1)[ch][idx[1]] * (gx[:, idx[2]] * gz[:, idx[0]]).T).sum(axis=1)
+            out[ch][idx] = (vals + core_value).astype(np.float32)
+    return out
+
+
+def pocket_grid_values_direct(edge: int, spacing: float, pseudo_xyz: np.ndarray,
+                              pseudo_w: np.ndarray, sigma: float = 1.2, core_radius: float = 1.2,
+                              core_value: float = 10.0) -> np.ndarray:
+    """The same texels by the literal formula (slow; used to check the separable form)."""
     n = int(edge)
     c = pseudo_w.shape[1]
     origin = -spacing * (n - 1) / 2.0
@@ -148,18 +193,15 @@ def pocket_grid_values(edge: int, spacing: float, pseudo_xyz: np.ndarray, pseudo
     out = np.empty((c, n, n, n), dtype=np.float32)
     two_s2 = 2.0 * sigma * sigma
     px, py, pz = pseudo_xyz[:, 0], pseudo_xyz[:, 1], pseudo_xyz[:, 2]
-    xx = axis[None, :]
-    dx2 = (axis[:, None] - px[None, :]) ** 2            # [n, 300]
-    for k in range(n):                                   # one z slice at a time
-        dz2 = (axis[k] - pz) ** 2                        # [300]
+    dx2 = (axis[:, None] - px[None, :]) ** 2
+    for k in range(n):
+        dz2 = (axis[k] - pz) ** 2
         d2 = (dz2[None, None, :] + ((axis[:, None] - py[None, :]) ** 2)[:, None, :]
-              + dx2[None, :, :])                         # [y, x, 300]
-        d2 = d2.reshape(n * n, -1)
-        g = np.exp(-d2 / two_s2) @ pseudo_w              # [n*n, C]
+              + dx2[None, :, :]).reshape(n * n, -1)
+        g = np.exp(-d2 / two_s2) @ pseudo_w
         core = np.sqrt(d2.min(axis=1)) < core_radius
         g[core] += core_value
         out[:, k, :, :] = g.T.reshape(c, n, n).astype(np.float32)
-    del xx
     return out
 
 

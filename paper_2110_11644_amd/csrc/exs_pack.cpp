@@ -117,6 +117,12 @@ int pack_ligand(int n, const int32_t* bond_ij, int nb, const int32_t* rot_bond, 
             return EXS_EINVAL;
         }
         side.clear(v);
+        const double ax = (double)x[v] - x[u], ay = (double)y[v] - y[u], az = (double)z[v] - z[u];
+        if (!(ax * ax + ay * ay + az * az > 1e-12)) {
+            snprintf(buf, sizeof buf, "rotatable bond %d (%d-%d) has zero length", b, p, q);
+            *err = buf;
+            return EXS_EINVAL;
+        }
         out->rot_u[b] = u;
         out->rot_v[b] = v;
         out->moving[b] = side;

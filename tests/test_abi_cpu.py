@@ -65,7 +65,7 @@ def test_moving_sets_closed_form(B):
     assert t["rot_u"].tolist() == [1, 3] and t["rot_v"].tolist() == [2, 4]
     assert np.flatnonzero(t["moving"][0]).tolist() == [3, 4, 5]
     assert np.flatnonzero(t["moving"][1]).tolist() == [5]
-    rev = Lig(np.zeros((4, 3)), np.zeros(4), [[2, 1], [0, 1], [3, 2]], [0])
+    rev = Lig(np.arange(12.0).reshape(4, 3), np.zeros(4), [[2, 1], [0, 1], [3, 2]], [0])
     t = B.exs_pack_topology(rev, 1)
     assert (t["rot_u"][0], t["rot_v"][0]) == (1, 2)
     assert np.flatnonzero(t["moving"][0]).tolist() == [3]
@@ -83,12 +83,13 @@ def test_packing_matches_oracle_bfs(B, oracle_lib):
 
 
 @pytest.mark.parametrize("case", ["ring", "type", "bond_index", "rot_index", "too_many_atoms",
-                                  "too_many_rot", "self_bond", "not_finite", "disconnected_rot"])
+                                  "too_many_rot", "self_bond", "not_finite", "disconnected_rot",
+                                  "zero_length_axis"])
 def test_invalid_ligands_are_rejected(B, case):
     lig = chain(6, rot=[2])
     channels = 2
     if case == "ring":
-        lig = Lig(np.zeros((4, 3)), np.zeros(4), [[0, 1], [1, 2], [2, 0], [2, 3]], [0])
+        lig = Lig(np.arange(12.0).reshape(4, 3), np.zeros(4), [[0, 1], [1, 2], [2, 0], [2, 3]], [0])
     elif case == "type":
         lig.types[3] = 2
     elif case == "bond_index":
@@ -103,8 +104,10 @@ def test_invalid_ligands_are_rejected(B, case):
         lig.bonds[1] = [2, 2]
     elif case == "not_finite":
         lig.xyz[1, 2] = np.nan
+    elif case == "zero_length_axis":
+        lig.xyz[3] = lig.xyz[2]
     elif case == "disconnected_rot":
-        lig = Lig(np.zeros((5, 3)), np.zeros(5), [[0, 1], [2, 3], [3, 4]], [2])
+        lig = Lig(np.arange(15.0).reshape(5, 3), np.zeros(5), [[0, 1], [2, 3], [3, 4]], [2])
     with pytest.raises(B.ExsError) as ei:
         B.exs_pack_topology(lig, channels)
     assert ei.value.code == B.EXS_EINVAL
