@@ -75,20 +75,31 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Fill the turn tables of the current device from FP64 host values.
+// Fill the turn tables of the current device: FP32 from the quarter-period literals (the
+// same values the unrolled kernels use), checked against FP64 cos / sin rounded to FP32;
+// FP64 from the host's cos / sin.
+template <int S>
+static bool fill_trig(float* t32, double* t64) {
+    const int off = trig_offset(S);
+    bool ok = true;
+    for (int s = 0; s < S; ++s) {
+        double a = 2.0 * 3.14159265358979323846 * (double)s / (double)S;
+        double c = (4 * s == S || 4 * s == 3 * S) ? 0.0 : (s == 0 ? 1.0 : cos(a));
+        double sn = (s == 0 || 2 * s == S) ? 0.0 : (4 * s == S ? 1.0 : (4 * s == 3 * S ? -1.0 : sin(a)));
+        t64[off + s] = c;
+        t64[off + S + s] = sn;
+        t32[off + s] = kcos<S>(s);
+        t32[off + S + s] = ksin<S>(s);
+        ok = ok && t32[off + s] == (float)c && t32[off + S + s] == (float)sn;
+    }
+    return ok;
+}
+
 hipError_t upload_trig_tables() {
     float t32[kTrigEntries];
     double t64[kTrigEntries];
-    const int steps[3] = {8, 16, 32};
-    for (int si = 0; si < 3; ++si) {
-        int S = steps[si], off = trig_offset(S);
-        for (int s = 0; s < S; ++s) {
-            double a = 2.0 * 3.14159265358979323846 * (double)s / (double)S;
-            double c = s == 0 ? 1.0 : cos(a), sn = s == 0 ? 0.0 : sin(a);
-            t64[off + s] = c; t64[off + S + s] = sn;
-            t32[off + s] = (float)c; t32[off + S + s] = (float)sn;
-        }
-    }
+    if (!fill_trig<8>(t32, t64) || !fill_trig<16>(t32, t64) || !fill_trig<32>(t32, t64))
+        return hipErrorInvalidValue;   // a literal of the quarter-period table is wrong
     hipError_t e = upload_trig_f32(t32, t64);
     if (e == hipSuccess) e = upload_trig_bf16(t32, t64);
     if (e == hipSuccess) e = upload_trig_f16(t32, t64);

@@ -18,6 +18,35 @@ constexpr int kMaxThreadsPerWg = kMaxWavesPerWg * kWave;
 constexpr int kTrigEntries = 2 * (8 + 16 + 32);
 __host__ __device__ constexpr int trig_offset(int S) { return S == 8 ? 0 : (S == 16 ? 16 : 48); }
 
+// cos(2 pi m / S) for 0 <= m <= S/4, FP64 values rounded to FP32 (RNE).  Every turn
+// 2 pi s / S of the torsion sweep has cos and sin equal to +-qcos(m) for some m, so the
+// unrolled sweep needs S/4 + 1 constants and the signs fold into FMA source modifiers.
+// upload_trig_tables() checks these literals against the host's FP64 cos.
+template <int S> __host__ __device__ __forceinline__ constexpr float qcos(int m);
+template <> __host__ __device__ __forceinline__ constexpr float qcos<8>(int m) {
+    return m == 0 ? 1.0f : (m == 1 ? 0x1.6a09e6p-1f : 0.0f);
+}
+template <> __host__ __device__ __forceinline__ constexpr float qcos<16>(int m) {
+    return m == 0 ? 1.0f : m == 1 ? 0x1.d906bcp-1f : m == 2 ? 0x1.6a09e6p-1f
+         : m == 3 ? 0x1.87de2ap-2f : 0.0f;
+}
+template <> __host__ __device__ __forceinline__ constexpr float qcos<32>(int m) {
+    return m == 0 ? 1.0f : m == 1 ? 0x1.f6297cp-1f : m == 2 ? 0x1.d906bcp-1f
+         : m == 3 ? 0x1.a9b662p-1f : m == 4 ? 0x1.6a09e6p-1f : m == 5 ? 0x1.1c73b4p-1f
+         : m == 6 ? 0x1.87de2ap-2f : m == 7 ? 0x1.8f8b84p-3f : 0.0f;
+}
+// cos and sin of 2 pi s / S, 0 <= s < S, from the quarter-period table.
+template <int S> __host__ __device__ __forceinline__ constexpr float kcos(int s) {
+    constexpr int Q = S / 4;
+    const int q = s / Q, r = s % Q;
+    return q == 0 ? qcos<S>(r) : q == 1 ? -qcos<S>(Q - r) : q == 2 ? -qcos<S>(r) : qcos<S>(Q - r);
+}
+template <int S> __host__ __device__ __forceinline__ constexpr float ksin(int s) {
+    constexpr int Q = S / 4;
+    const int q = s / Q, r = s % Q;
+    return q == 0 ? qcos<S>(Q - r) : q == 1 ? qcos<S>(r) : q == 2 ? -qcos<S>(Q - r) : -qcos<S>(r);
+}
+
 // One packed ligand (caller order).
 struct LigInfo {
     int32_t atom_base;   // first atom in the packed atom arrays
