@@ -64,7 +64,23 @@ def algorithmic_counts(binding, batch, search, channels):
     return L, Q, R
 
 
-def cpu_baseline(workload, pocket, batch, search, max_ligands=256, budget_s=25.0):
+def measured_traffic(n_ligands):
+    """HBM bytes of one dock launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
+    or None if the dock kernel's source changed since those counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "dock_kernel_scale_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_2110_11644_amd", "csrc", "dock_kernels.inc"), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != h:
+        return None
+    return float(rec["hbm_bytes_per_dock"]) * n_ligands
+
+
+def cpu_baseline(workload, pocket, batch, search, max_ligands=1024, budget_s=20.0):
     """The FP64 oracle as it stands, OpenMP over ligands on the host cores, on a bounded
     prefix of the same workload (chunks of 32 ligands until the time budget is spent)."""
     import oracle as O
@@ -172,6 +188,10 @@ def main():
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
     alu = {"bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
            "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None}
+    traffic = measured_traffic(L) if (args.workload == "scale" and storage == 0 and args.ppl in (0, 1)
+                                      and args.lpw in (0, 1) and not args.persistent) else None
+    mem["traffic"] = traffic
+    alu["traffic"] = traffic
     roof, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
     roof = dict(roof)
     roof["kernel"] = "exs::dock_kernel"
