@@ -102,12 +102,348 @@ def cpu_baseline(workload, pocket, batch, search, max_ligands=1024, budget_s=20.
                       "FP64 oracle, OpenMP over ligands, %.1f s" % (done, workload, dt)}
 
 
+def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1):
+    """Roofline objects (texel bytes vs HBM peak, FP32 lane-ops vs VALU peak) of one launch over
+    `batch`; the algorithmic counts come from every `sample_every`-th ligand, scaled."""
+    idx = list(range(0, batch.n_ligands, sample_every))
+    sub = batch if sample_every == 1 else batch.subset(idx)
+    Lk, Qk, Rk = algorithmic_counts(B, sub, search, channels)
+    scale = batch.n_ligands / sub.n_ligands
+    K = search.n_orient
+    tex_bytes = 8.0 * (4.0 if storage == 0 else 2.0) * K * Lk.sum() * scale
+    ops = K * (30.0 * Lk.sum() + 7.0 * Qk.sum() + 15.0 * Rk.sum()) * scale
+    gbs = tex_bytes / (kernel_ms * 1e-3) / 1e9
+    tops = ops / (kernel_ms * 1e-3) / 1e12
+    mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    alu = {"bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS,
+           "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None}
+    roof, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
+    roof = dict(roof)
+    roof["kernel"] = "exs::dock_kernel"
+    roof["kernel_ms"] = round(kernel_ms, 3)
+    roof["other"] = other
+    if sample_every > 1:
+        roof["counts_sampled_every"] = sample_every
+    return roof
+
+
+def load_batched_pockets(S, B, storage, stream, log=True, pockets=None):
+    wl = S.BATCHED
+    if pockets is None:
+        pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+    pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin, storage, stream=stream)
+            for p in pockets]
+    if log:
+        progress("loaded %d pockets, edges %s" % (len(pids), [p.n for p in pockets]))
+    return pockets, pids
+
+
+def timed_steps(B, torch, bid, prm, L, A, steps, warmup, stream, top_k=0):
+    def step():
+        job = B.exs_dock_batch(bid, prm, stream=stream)
+        out = B.exs_get_best_poses(job, L, A, top_k=top_k, coords=True)
+        ms = B.exs_job_elapsed_ms(job)
+        B.exs_release_job(job)
+        return ms, out
+    for w in range(warmup):
+        ms, _ = step()
+        progress("warmup %d: %.1f ms" % (w, ms))
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    out = None
+    for i in range(steps):
+        ms, out = step()
+        kms.append(ms)
+        progress("step %d: %.1f ms" % (i, ms))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, float(np.mean(kms)), out
+
+
+def run_batched(args, torch, S, B):
+    """Uneven ligands over the 15 resident pockets in one persistent launch captured in a
+    hipGraph; tile from the autotuner (--tune) or --ppl / --lpw."""
+    from paper_2110_11644_amd import autotune
+    wl, s = S.BATCHED, S.BATCHED.search
+    stream = torch.cuda.current_stream()
+    storage = B.STORAGE[args.storage]
+    pockets, pids = load_batched_pockets(S, B, storage, stream)
+    L = args.ligands or wl.n_ligands
+    progress("generating %d ligands" % L)
+    batch = S.make_ligand_batch(wl, 0, L)
+    bid = B.exs_upload_ligands(batch, pocket_ids=pids, stream=stream)
+    flags = B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH
+    ppl, lpw, tuned = args.ppl or 1, args.lpw or 1, None
+    if args.tune:
+        sample = batch.subset(range(0, L, max(1, L // 4096)))
+        sid = B.exs_upload_ligands(sample, pocket_ids=pids, stream=stream)
+        tuned = autotune.tune(sid, s, storage, B.EXS_FLAG_PERSISTENT,
+                              float(np.diff(sample.atom_offset).mean()), use_cache=False,
+                              stream=stream, log=progress)
+        B.exs_release_ligands(sid)
+        ppl, lpw = tuned["ppl"], tuned["lpw"]
+    prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                          s.clash_cutoff, s.clash_penalty, poses_per_lane=ppl, ligands_per_wg=lpw,
+                          flags=flags)
+    A = int(batch.atom_offset[-1])
+    dt, kms, out = timed_steps(B, torch, bid, prm, L, A, args.steps, args.warmup, stream)
+    assert np.all(np.isfinite(out["best_score"]))
+    value = L * args.steps / dt
+    progress("counting algorithmic work (sampled)")
+    roof = roofline_of(B, batch, s, 8, kms, storage, sample_every=max(1, L // 10000))
+    B.exs_release_ligands(bid)
+    for pid in pids:
+        B.exs_unload_pocket(pid)
+    line = {
+        "metric": "ligand-pocket docks/sec on 1 MI355X (batched)", "value": round(value, 2),
+        "unit": "docks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if storage == 0 else args.storage,
+        "data": "synthetic",
+        "config": {"workload": "batched: %d ligands (log-normal atoms, median 35, 10-90; 0-15 "
+                               "rotatable bonds) over 15 resident pockets (edges %s, 8 ch, 0.375 A); "
+                               "K=256, S=32, P=2, T=27; one persistent launch in a hipGraph" % (
+                                   L, sorted(set(p.n for p in pockets))),
+                   "ligands": L, "atoms": A, "poses_per_lane": ppl, "ligands_per_wg": lpw,
+                   "tile_timings_ms": None if tuned is None else tuned["timings"],
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def top_set(scores, frac):
+    n = max(1, int(round(len(scores) * frac)))
+    order = np.lexsort((np.arange(len(scores)), scores))   # score ascending, ties by ligand id
+    return set(order[:n].tolist())
+
+
+def run_precision(args, torch, S, B):
+    """BF16 and FP16 texels (FP32 interpolation) with FP64 rescoring of the top 8 poses,
+    against the FP32 path (all ligands) and the FP64 oracle (a prefix sample)."""
+    import oracle as O
+    wl, s = S.BATCHED, S.PRECISION.search
+    stream = torch.cuda.current_stream()
+    L = args.ligands or wl.n_ligands
+    progress("generating %d ligands" % L)
+    batch = S.make_ligand_batch(wl, 0, L)
+    A = int(batch.atom_offset[-1])
+    flags = B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH
+    results = {}
+    pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+    for name, storage, top_k in (("f32", 0, 0), ("bf16", 1, 8), ("f16", 2, 8)):
+        pockets, pids = load_batched_pockets(S, B, storage, stream, log=(name == "f32"),
+                                             pockets=pockets)
+        bid = B.exs_upload_ligands(batch, pocket_ids=pids, stream=stream)
+        prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                              s.clash_cutoff, s.clash_penalty, top_k=top_k,
+                              poses_per_lane=args.ppl or 1, ligands_per_wg=args.lpw or 1,
+                              flags=flags)
+        dt, kms, out = timed_steps(B, torch, bid, prm, L, A, args.steps, args.warmup, stream,
+                                   top_k=top_k)
+        results[name] = dict(value=L * args.steps / dt, kernel_ms=kms, out=out)
+        progress("%s: %.0f docks/s" % (name, results[name]["value"]))
+        B.exs_release_ligands(bid)
+        for pid in pids:
+            B.exs_unload_pocket(pid)
+    # FP64 oracle on a prefix sample (best score of each ligand)
+    M = min(args.oracle_sample, L)
+    progress("oracle on %d ligands" % M)
+    grids = [O.Grid.of(p) for p in pockets]
+    cores = len(os.sched_getaffinity(0))
+    ref = O.dock_batch(grids, O.Params.of(s), batch.subset(range(M)), threads=cores)
+    prm_o = O.Params.of(s)
+    report = {}
+    ref32 = results["f32"]["out"]["best_score"].astype(np.float64)
+    for name in ("bf16", "f16"):
+        out = results[name]["out"]
+        b64 = out["desc"]["score_fp64"].astype(np.float64)
+        err = np.abs(b64[:M] - ref["best_score"])
+        rel = err / np.maximum(np.abs(ref["best_score"]), 1.0)
+        rmsd = []
+        same = 0
+        for l in range(M):
+            lig = batch.ligand(l)
+            d = out["desc"][l]
+            X = O.pose_from_desc(grids[lig.pocket], prm_o, lig, int(d["orient"]),
+                                 d["theta"][:len(lig.rot)], d["tau"])
+            a0, a1 = int(batch.atom_offset[l]), int(batch.atom_offset[l + 1])
+            rmsd.append(float(np.sqrt(np.mean(np.sum((out["coords"][a0:a1] - X) ** 2, axis=1)))))
+            same += int(d["orient"]) == int(ref["best_k"][l])
+        report[name] = {
+            "docks_per_s": round(results[name]["value"], 1),
+            "kernel_ms": round(results[name]["kernel_ms"], 2),
+            "score_err_vs_oracle_max": float(err.max()), "score_err_vs_oracle_mean": float(err.mean()),
+            "score_relerr_vs_oracle_max": float(rel.max()),
+            "best_pose_rmsd_vs_fp64_rebuild_max_A": max(rmsd),
+            "best_orientation_equal_to_oracle": same / M,
+            "top1pct_overlap_vs_fp32_gpu_all": len(top_set(b64, 0.01) & top_set(ref32, 0.01))
+                                               / len(top_set(ref32, 0.01)),
+            "top1pct_overlap_vs_oracle_sample": len(top_set(b64[:M], 0.01)
+                                                    & top_set(ref["best_score"], 0.01))
+                                                / len(top_set(ref["best_score"], 0.01)),
+            "top10pct_overlap_vs_oracle_sample": len(top_set(b64[:M], 0.1)
+                                                     & top_set(ref["best_score"], 0.1))
+                                                 / len(top_set(ref["best_score"], 0.1)),
+        }
+    f32err = np.abs(ref32[:M] - ref["best_score"]) / np.maximum(np.abs(ref["best_score"]), 1.0)
+    line = {
+        "metric": "ligand-pocket docks/sec on 1 MI355X (16-bit texels + FP64 top-8 rescoring)",
+        "value": round(results["f16"]["value"], 2), "unit": "docks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16->f32 (+f64 rescoring)", "data": "synthetic",
+        "config": {"workload": "precision: the batched inputs (%d ligands, 15 pockets), texels "
+                               "BF16 and FP16, top_k=8 FP64 rescoring; FP32 run for reference" % L,
+                   "ligands": L, "oracle_sample": M, "parallelism": "single GPU"},
+        "fp32_docks_per_s": round(results["f32"]["value"], 1),
+        "fp32_relerr_vs_oracle_max": float(f32err.max()),
+        "precision": report,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args, torch, S, B):
+    """Poisson arrivals of requests (1-512 ligands, log-uniform, random pocket) at a fixed
+    offered load, served by the continuous-batching server; the same trace replayed with one
+    plain launch per request (FIFO) for comparison."""
+    import threading
+    s = S.SERVING.search
+    stream = torch.cuda.current_stream()
+    storage = B.STORAGE[args.storage]
+    pockets, pids = load_batched_pockets(S, B, storage, stream)
+    prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                          s.clash_cutoff, s.clash_penalty, poses_per_lane=args.ppl or 1,
+                          ligands_per_wg=args.lpw or 1, flags=B.EXS_FLAG_PERSISTENT)
+    # capacity: persistent launch over a sample of the request ligands
+    cap_batch = S.make_ligand_batch(S.BATCHED, 0, 4096)
+    cid = B.exs_upload_ligands(cap_batch, pocket_ids=pids, stream=stream)
+    _, cap_ms, _ = timed_steps(B, torch, cid, prm, cap_batch.n_ligands,
+                               int(cap_batch.atom_offset[-1]), 2, 1, stream)
+    B.exs_release_ligands(cid)
+    capacity = cap_batch.n_ligands / (cap_ms * 1e-3)
+    warm = max(10, args.requests // 20)
+    n_req = args.requests + warm
+    mean_size = 82.0
+    rate = args.load * capacity / mean_size
+    trace = S.make_trace(n_req, rate)
+    progress("capacity %.0f docks/s, %d requests at %.1f req/s (load %.2f)" % (
+        capacity, n_req, rate, args.load))
+    reqs = []
+    for r in trace:
+        ligs = S.serving_ligands(r)
+        b = S.batch_from_ligands(ligs)
+        b.pocket_id[:] = r.pocket
+        reqs.append(b)
+    progress("generated %d ligands" % sum(b.n_ligands for b in reqs))
+
+    def replay(submit, finish):
+        """Submit at the trace's arrival times; returns per-request latency (s) and span."""
+        lat = [None] * n_req
+        done_t = [None] * n_req
+        handles = [None] * n_req
+        ready = [threading.Event() for _ in range(n_req)]
+        t0 = time.perf_counter()
+
+        def waiter():
+            for i in range(n_req):
+                ready[i].wait()
+                finish(handles[i], reqs[i])
+                done_t[i] = time.perf_counter()
+                lat[i] = done_t[i] - (t0 + trace[i].arrival_s)
+        th = threading.Thread(target=waiter)
+        th.start()
+        for i, r in enumerate(trace):
+            now = time.perf_counter() - t0
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            handles[i] = submit(reqs[i])
+            ready[i].set()
+        th.join()
+        return np.array(lat), t0, done_t
+
+    srv = B.exs_server_create(pids, prm, hbm_budget_bytes=8 << 30)
+    lat_s, t0s, done_s = replay(
+        lambda b: B.exs_server_submit(srv, b, pocket_ids=pids),
+        lambda h, b: B.exs_server_poll(srv, h, b.n_ligands, int(b.atom_offset[-1])))
+    stats = B.exs_server_get_stats(srv)
+    B.exs_server_destroy(srv)
+    progress("served: p50 %.1f ms p99 %.1f ms" % (np.percentile(lat_s[warm:], 50) * 1e3,
+                                                 np.percentile(lat_s[warm:], 99) * 1e3))
+    # plain per-request launch: one upload + dock + fetch per request, in arrival order
+    import queue
+    q = queue.Queue()
+    results = {}
+
+    def plain_worker():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            i, b = item
+            bid = B.exs_upload_ligands(b, pocket_ids=pids, stream=stream)
+            prm_p = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets,
+                                    s.offset_step, s.clash_cutoff, s.clash_penalty,
+                                    poses_per_lane=args.ppl or 1, ligands_per_wg=args.lpw or 1)
+            job = B.exs_dock_batch(bid, prm_p, stream=stream)
+            B.exs_get_best_poses(job, b.n_ligands, int(b.atom_offset[-1]))
+            B.exs_release_job(job)
+            B.exs_release_ligands(bid)
+            results[i].set()
+    wk = threading.Thread(target=plain_worker)
+    wk.start()
+    counter = [0]
+
+    def plain_submit(b):
+        i = counter[0]
+        counter[0] += 1
+        results[i] = threading.Event()
+        q.put((i, b))
+        return i
+    lat_p, t0p, done_p = replay(plain_submit, lambda h, b: results[h].wait())
+    q.put(None)
+    wk.join()
+    for pid in pids:
+        B.exs_unload_pocket(pid)
+    timed_lig = sum(reqs[i].n_ligands for i in range(warm, n_req))
+    span_s = done_s[-1] - (t0s + trace[warm].arrival_s)
+    span_p = done_p[-1] - (t0p + trace[warm].arrival_s)
+    line = {
+        "metric": "ligand-pocket docks/sec on 1 MI355X (served), p50/p99 latency",
+        "value": round(timed_lig / span_s, 2), "unit": "docks/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": warm, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if storage == 0 else args.storage, "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals at %.2f x capacity (%.0f docks/s), "
+                               "requests of 1-512 ligands (log-uniform) against one of 15 resident "
+                               "pockets; continuous batching vs one plain launch per request" % (
+                                   args.load, capacity),
+                   "requests": args.requests, "warmup_requests": warm,
+                   "ligands": timed_lig, "parallelism": "single GPU"},
+        "served": {"p50_ms": round(float(np.percentile(lat_s[warm:], 50)) * 1e3, 2),
+                   "p99_ms": round(float(np.percentile(lat_s[warm:], 99)) * 1e3, 2),
+                   "docks_per_s": round(timed_lig / span_s, 1), "iterations": stats["iterations"]},
+        "plain_per_request": {"p50_ms": round(float(np.percentile(lat_p[warm:], 50)) * 1e3, 2),
+                              "p99_ms": round(float(np.percentile(lat_p[warm:], 99)) * 1e3, 2),
+                              "docks_per_s": round(timed_lig / span_p, 1)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="scale", choices=["scale", "small"])
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "small", "batched", "precision", "serving"])
+    ap.add_argument("--tune", action="store_true", help="autotune the tile (batched)")
+    ap.add_argument("--requests", type=int, default=600, help="serving: timed requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
+    ap.add_argument("--oracle-sample", type=int, default=192,
+                    help="precision: ligands checked against the FP64 oracle")
     ap.add_argument("--ligands", type=int, default=None, help="override the ligand count")
     ap.add_argument("--ppl", type=int, default=0)
     ap.add_argument("--lpw", type=int, default=0)
@@ -137,6 +473,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
         return
+    if args.workload == "batched":
+        return run_batched(args, torch, S, B)
+    if args.workload == "precision":
+        return run_precision(args, torch, S, B)
+    if args.workload == "serving":
+        return run_serving(args, torch, S, B)
     wl = S.WORKLOADS[args.workload]
     s = wl.search
     n_lig = args.ligands or wl.n_ligands
