@@ -740,7 +740,10 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         j->device = dev; j->batch = b; j->prm = p; j->stream = st;
         j->L = b->L; j->A = b->A; j->R = b->R; j->K = K; j->top_k = top_k;
         const int L = b->L;
-        const size_t lds = dock_lds_bytes(lpw, top_k);
+        const size_t lds = dock_lds_bytes(lpw, top_k, lpw * wpl, ppl, p.torsion_steps);
+        if (lds > kMaxLdsBytes)
+            return fail(EXS_EINVAL, "tile of %d ligands x %d waves x %d poses per lane needs %zu B of LDS (max %zu)",
+                        lpw, wpl, ppl, lds, kMaxLdsBytes);
         const void* fn = dock_kernel_fn(storage < 0 ? 0 : storage, p.torsion_steps, ppl);
         if (!fn) return fail(EXS_EINVAL, "no kernel for this configuration");
         if (lds > 64 * 1024) {

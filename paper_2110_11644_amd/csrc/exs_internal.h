@@ -133,10 +133,16 @@ struct LigLds {
     int32_t topk[kMaxTopK];
 };
 
-// Dynamic LDS bytes of a dock launch.
-inline size_t dock_lds_bytes(int lpw, int top_k) {
-    return (size_t)lpw * sizeof(LigLds) + (top_k > 0 ? (size_t)lpw * kMaxAtoms * 3 * sizeof(double) : 0);
+// Dynamic LDS bytes of a dock launch: the tile's ligands, the FP64 rescoring poses (top_k > 0)
+// and, per wave, a clash difference array of S counters per pose slot and lane.
+__host__ __device__ inline size_t dock_lds_x64_offset(int lpw) { return (size_t)lpw * sizeof(LigLds); }
+__host__ __device__ inline size_t dock_lds_diff_offset(int lpw, int top_k) {
+    return dock_lds_x64_offset(lpw) + (top_k > 0 ? (size_t)lpw * kMaxAtoms * 3 * sizeof(double) : 0);
 }
+__host__ __device__ inline size_t dock_lds_bytes(int lpw, int top_k, int waves, int ppl, int S) {
+    return dock_lds_diff_offset(lpw, top_k) + (size_t)waves * ppl * S * kWave * sizeof(int32_t);
+}
+constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 
 // Launchers (dock_kernels.hip).
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,

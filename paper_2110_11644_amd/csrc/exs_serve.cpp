@@ -209,7 +209,8 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
         return rt::fail(EXS_EINVAL, "ligands_per_wg %d does not fit a workgroup", lpw_);
     threads_ = lpw_ * wpl_ * kWave;
     top_k_ = std::min(p.top_k, K_);
-    lds_ = dock_lds_bytes(lpw_, top_k_);
+    lds_ = dock_lds_bytes(lpw_, top_k_, lpw_ * wpl_, ppl_, p.torsion_steps);
+    if (lds_ > kMaxLdsBytes) return rt::fail(EXS_EINVAL, "tile needs %zu B of LDS", lds_);
     n_iters_ = cfg.max_inflight_iters == 1 ? 1 : 2;
     // pockets
     std::vector<GridDesc> grids;
@@ -225,6 +226,8 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
         grids.push_back(pi.desc);
     }
     const void* fn = dock_kernel_fn(storage_, p.torsion_steps, ppl_);
+    if (lds_ > 64 * 1024)
+        SRV_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_));
     int per_cu = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_, lds_) != hipSuccess || per_cu < 1)
         per_cu = 1;
