@@ -70,8 +70,11 @@ const char* exs_last_error(void);
  *               centre, where each ligand's centroid is placed.
  *   storage     EXS_F32, EXS_BF16 or EXS_F16: texels are stored in this type
  *               (round to nearest even); interpolation and accumulation run in
- *               FP32.  The FP32 master copy is always kept as well: it feeds
- *               the FP64 rescoring of the top poses.
+ *               FP32.  16-bit texels are kept as packed x-neighbour pairs (one
+ *               4-byte word per texel holds it and its +x neighbour), so a
+ *               corner pair is one 4-byte gather instead of the 8 bytes of FP32.
+ *               The FP32 master copy is always kept as well: it feeds the FP64
+ *               rescoring of the top poses.
  *   pocket_id_out  receives the handle.
  * Errors: EXS_EINVAL (bad sizes, channels > EXS_MAX_CHANNELS, non-finite
  * texels), EXS_ENOMEM, EXS_EDEVICE.

@@ -18,19 +18,25 @@ hipError_t upload_trig_f16(const float* t32, const double* t64);
 
 
 
-// FP32 -> 16-bit texels, round to nearest even.
-__global__ void convert_grid_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
-                                    int64_t count, int storage) {
+// FP32 -> 16-bit texels (round to nearest even), stored as packed x-pairs: element i holds
+// V[i] in its low half and V[i+1] in its high half (V[i] twice at the last x of a row).
+__device__ __forceinline__ uint32_t to16(float v, int storage) {
+    if (storage == 1) {                       // BF16
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return u >> 16;
+    }
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);   // FP16
+}
+
+__global__ void convert_grid_kernel(const float* __restrict__ src, uint32_t* __restrict__ dst,
+                                    int64_t count, int nx, int storage) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        float v = src[i];
-        if (storage == 1) {                       // BF16
-            uint32_t u = __builtin_bit_cast(uint32_t, v);
-            u += 0x7fffu + ((u >> 16) & 1u);
-            dst[i] = (uint16_t)(u >> 16);
-        } else {                                  // FP16
-            dst[i] = __builtin_bit_cast(uint16_t, (_Float16)v);
-        }
+        const bool last = (i % nx) == nx - 1;
+        const uint32_t lo = to16(src[i], storage);
+        const uint32_t hi = last ? lo : to16(src[i + 1], storage);
+        dst[i] = lo | (hi << 16);
     }
 }
 
@@ -60,13 +66,13 @@ const void* dock_kernel_fn(int storage, int S, int ppl) {
     }
 }
 
-hipError_t launch_convert_grid(const float* src, uint16_t* dst, int64_t count, int storage,
+hipError_t launch_convert_grid(const float* src, uint32_t* dst, int64_t count, int nx, int storage,
                                hipStream_t st) {
     int64_t blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(convert_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst,
-                       count, storage);
+                       count, nx, storage);
     return hipGetLastError();
 }
 

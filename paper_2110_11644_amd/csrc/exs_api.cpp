@@ -124,7 +124,7 @@ struct Pocket {
     int nx = 0, ny = 0, nz = 0, channels = 0, storage = EXS_F32;
     double h = 0, origin[3] = {0, 0, 0};
     float* master = nullptr;     // FP32 texels
-    uint16_t* half = nullptr;    // 16-bit texels (storage != F32)
+    uint32_t* half = nullptr;    // 16-bit texels as packed x-pairs (storage != F32)
     GridDesc desc;
     std::atomic<int> users{0};
 };
@@ -297,8 +297,8 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         HIP_TRY(hipMemcpyAsync(p->master, values, (size_t)count * sizeof(float),
                                values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
         if (storage != EXS_F32) {
-            HIP_TRY(hipMalloc(&p->half, (size_t)count * sizeof(uint16_t)));
-            HIP_TRY(launch_convert_grid(p->master, p->half, count, storage, st));
+            HIP_TRY(hipMalloc(&p->half, (size_t)count * sizeof(uint32_t)));
+            HIP_TRY(launch_convert_grid(p->master, p->half, count, nx, storage, st));
         }
         HIP_TRY(hipStreamSynchronize(st));
         GridDesc& g = p->desc;
@@ -313,7 +313,7 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         g.dcy = origin_A[1] + spacing_A * (ny - 1) / 2.0;
         g.dcz = origin_A[2] + spacing_A * (nz - 1) / 2.0;
         g.cx = (float)g.dcx; g.cy = (float)g.dcy; g.cz = (float)g.dcz;
-        g.chan_bytes = (int32_t)(chan * (storage == EXS_F32 ? 4 : 2));
+        g.chan_bytes = (int32_t)(chan * 4);
         g.master_chan_bytes = (int32_t)(chan * 4);
         g.storage = storage;
         std::lock_guard<std::mutex> lk(g_reg_mu);

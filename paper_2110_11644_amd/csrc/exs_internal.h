@@ -62,7 +62,7 @@ static_assert(sizeof(LigInfo) == 32, "LigInfo layout");
 
 // One pocket as the kernels see it.
 struct GridDesc {
-    const void* tex;       // storage texels [C][nz][ny][nx] (FP32, BF16 or FP16)
+    const void* tex;       // storage texels [C][nz][ny][nx]: FP32, or packed 16-bit x-pairs
     const float* master;   // FP32 master texels, same layout
     int nx, ny, nz, channels;
     float ox, oy, oz, inv_h;   // origin and 1/spacing, FP32
@@ -147,7 +147,7 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 // Launchers (dock_kernels.hip).
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
                        size_t lds, hipStream_t st);
-hipError_t launch_convert_grid(const float* src, uint16_t* dst, int64_t count, int storage,
+hipError_t launch_convert_grid(const float* src, uint32_t* dst, int64_t count, int nx, int storage,
                                hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 hipError_t upload_trig_tables();
