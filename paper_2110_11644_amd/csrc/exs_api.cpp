@@ -313,6 +313,9 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         g.dcy = origin_A[1] + spacing_A * (ny - 1) / 2.0;
         g.dcz = origin_A[2] + spacing_A * (nz - 1) / 2.0;
         g.cx = (float)g.dcx; g.cy = (float)g.dcy; g.cz = (float)g.dcz;
+        g.ux_hi = nextafterf((float)(nx - 1), 0.0f);
+        g.uy_hi = nextafterf((float)(ny - 1), 0.0f);
+        g.uz_hi = nextafterf((float)(nz - 1), 0.0f);
         g.chan_bytes = (int32_t)(chan * 4);
         g.master_chan_bytes = (int32_t)(chan * 4);
         g.storage = storage;

@@ -67,6 +67,7 @@ struct GridDesc {
     int nx, ny, nz, channels;
     float ox, oy, oz, inv_h;   // origin and 1/spacing, FP32
     float cx, cy, cz, pad;     // pocket centre (grid centre), FP32
+    float ux_hi, uy_hi, uz_hi, pad1;  // largest floats below N-1 per axis (grid-unit clamp)
     double h, dox, doy, doz;   // FP64 geometry for the rescoring
     double dcx, dcy, dcz, dpad;
     int32_t chan_bytes;        // bytes of one storage channel
