@@ -18,8 +18,7 @@ hipError_t upload_trig_f16(const float* t32, const double* t64);
 
 
 
-// FP32 -> 16-bit texels (round to nearest even), stored as packed x-pairs: element i holds
-// V[i] in its low half and V[i+1] in its high half (V[i] twice at the last x of a row).
+// FP32 -> 16-bit texel bits, round to nearest even.
 __device__ __forceinline__ uint32_t to16(float v, int storage) {
     if (storage == 1) {                       // BF16
         uint32_t u = __builtin_bit_cast(uint32_t, v);
@@ -29,14 +28,39 @@ __device__ __forceinline__ uint32_t to16(float v, int storage) {
     return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);   // FP16
 }
 
-__global__ void convert_grid_kernel(const float* __restrict__ src, uint32_t* __restrict__ dst,
-                                    int64_t count, int nx, int storage) {
+// Expand the FP32 master [C][nz][ny][nx] (x fastest) into the per-cell gather layout, one
+// 16-byte entry per thread; entries of a channel are indexed (z * cy + y) * cx + x with
+// cx = nx-1, cy = ny-1.
+//  FP32 (storage 0): nz slices of quads {V(x,y,z), V(x+1,y,z), V(x,y+1,z), V(x+1,y+1,z)}.
+//  16-bit (1 BF16, 2 FP16): nz-1 slices of octets, dword j = corner(2j) | corner(2j+1) << 16,
+//  corner index dx + 2 dy + 4 dz.
+__global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restrict__ dst,
+                                   int nx, int ny, int nz, int64_t per_chan, int64_t count,
+                                   int storage) {
+    const int cx = nx - 1, cy = ny - 1;
+    const int64_t nxy = (int64_t)nx * ny, chan = nxy * nz;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const bool last = (i % nx) == nx - 1;
-        const uint32_t lo = to16(src[i], storage);
-        const uint32_t hi = last ? lo : to16(src[i + 1], storage);
-        dst[i] = lo | (hi << 16);
+        const int64_t c = i / per_chan, e = i - c * per_chan;
+        const int x = (int)(e % cx);
+        const int64_t yz = e / cx;
+        const int y = (int)(yz % cy), z = (int)(yz / cy);
+        const float* b = src + c * chan + (int64_t)z * nxy + (int64_t)y * nx + x;
+        uint4 o;
+        if (storage == 0) {
+            o.x = __builtin_bit_cast(uint32_t, b[0]);
+            o.y = __builtin_bit_cast(uint32_t, b[1]);
+            o.z = __builtin_bit_cast(uint32_t, b[nx]);
+            o.w = __builtin_bit_cast(uint32_t, b[nx + 1]);
+        } else {
+            uint32_t w[4];
+            for (int j = 0; j < 4; ++j) {
+                const float* r = b + (j >> 1) * nxy + (j & 1) * nx;   // (dy, dz) = (j & 1, j >> 1)
+                w[j] = to16(r[0], storage) | (to16(r[1], storage) << 16);
+            }
+            o = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        dst[i] = o;
     }
 }
 
@@ -66,13 +90,19 @@ const void* dock_kernel_fn(int storage, int S, int ppl) {
     }
 }
 
-hipError_t launch_convert_grid(const float* src, uint32_t* dst, int64_t count, int nx, int storage,
-                               hipStream_t st) {
+int64_t expanded_entries(int nx, int ny, int nz, int storage) {
+    return (int64_t)(nx - 1) * (ny - 1) * (storage == 0 ? nz : nz - 1);
+}
+
+hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,
+                              int storage, hipStream_t st) {
+    const int64_t per_chan = expanded_entries(nx, ny, nz, storage);
+    const int64_t count = per_chan * channels;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(convert_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst,
-                       count, nx, storage);
+    hipLaunchKernelGGL(expand_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src,
+                       static_cast<uint4*>(dst), nx, ny, nz, per_chan, count, storage);
     return hipGetLastError();
 }
 

@@ -124,7 +124,7 @@ struct Pocket {
     int nx = 0, ny = 0, nz = 0, channels = 0, storage = EXS_F32;
     double h = 0, origin[3] = {0, 0, 0};
     float* master = nullptr;     // FP32 texels
-    uint32_t* half = nullptr;    // 16-bit texels as packed x-pairs (storage != F32)
+    void* tex = nullptr;         // per-cell gather layout (FP32 quads or 16-bit octets)
     GridDesc desc;
     std::atomic<int> users{0};
 };
@@ -279,7 +279,9 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         if (storage != EXS_F32 && storage != EXS_BF16 && storage != EXS_F16)
             return fail(EXS_EINVAL, "unknown storage %d", storage);
         const int64_t chan = (int64_t)nx * ny * nz;
-        if (chan * 4 > INT32_MAX) return fail(EXS_EINVAL, "a grid channel must be < 2 GiB");
+        const int64_t tex_chan_bytes = expanded_entries(nx, ny, nz, storage) * 16;
+        if (tex_chan_bytes > INT32_MAX)
+            return fail(EXS_EINVAL, "a grid channel must expand to < 2 GiB (16 B per cell)");
         const int64_t count = chan * channels;
         if (!values_on_device) {
             for (int64_t i = 0; i < count; ++i)
@@ -293,17 +295,24 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         p->device = dev; p->nx = nx; p->ny = ny; p->nz = nz; p->channels = channels;
         p->storage = storage; p->h = spacing_A;
         for (int a = 0; a < 3; ++a) p->origin[a] = origin_A[a];
+        struct FreeOnFail {     // device buffers of a pocket whose load fails part way
+            Pocket* p;
+            bool armed = true;
+            ~FreeOnFail() {
+                if (!armed) return;
+                if (p->master) (void)hipFree(p->master);
+                if (p->tex) (void)hipFree(p->tex);
+            }
+        } guard{p.get()};
         HIP_TRY(hipMalloc(&p->master, (size_t)count * sizeof(float)));
         HIP_TRY(hipMemcpyAsync(p->master, values, (size_t)count * sizeof(float),
                                values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-        if (storage != EXS_F32) {
-            HIP_TRY(hipMalloc(&p->half, (size_t)count * sizeof(uint32_t)));
-            HIP_TRY(launch_convert_grid(p->master, p->half, count, nx, storage, st));
-        }
+        HIP_TRY(hipMalloc(&p->tex, (size_t)tex_chan_bytes * channels));
+        HIP_TRY(launch_expand_grid(p->master, p->tex, nx, ny, nz, channels, storage, st));
         HIP_TRY(hipStreamSynchronize(st));
         GridDesc& g = p->desc;
         memset(&g, 0, sizeof g);
-        g.tex = storage == EXS_F32 ? (const void*)p->master : (const void*)p->half;
+        g.tex = p->tex;
         g.master = p->master;
         g.nx = nx; g.ny = ny; g.nz = nz; g.channels = channels;
         g.ox = (float)origin_A[0]; g.oy = (float)origin_A[1]; g.oz = (float)origin_A[2];
@@ -316,12 +325,13 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         g.ux_hi = nextafterf((float)(nx - 1), 0.0f);
         g.uy_hi = nextafterf((float)(ny - 1), 0.0f);
         g.uz_hi = nextafterf((float)(nz - 1), 0.0f);
-        g.chan_bytes = (int32_t)(chan * 4);
+        g.chan_bytes = (int32_t)tex_chan_bytes;
         g.master_chan_bytes = (int32_t)(chan * 4);
         g.storage = storage;
         std::lock_guard<std::mutex> lk(g_reg_mu);
         int32_t id = g_next_pocket++;
         g_pockets[id] = p;
+        guard.armed = false;
         *pocket_id_out = id;
         return EXS_OK;
     } catch (const std::exception& e) {
@@ -343,7 +353,7 @@ int exs_unload_pocket(int32_t pocket_id) {
     }
     (void)hipDeviceSynchronize();
     if (p->master) (void)hipFree(p->master);
-    if (p->half) (void)hipFree(p->half);
+    if (p->tex) (void)hipFree(p->tex);
     return EXS_OK;
 }
 

@@ -70,7 +70,7 @@ struct GridDesc {
     float ux_hi, uy_hi, uz_hi, pad1;  // largest floats below N-1 per axis (grid-unit clamp)
     double h, dox, doy, doz;   // FP64 geometry for the rescoring
     double dcx, dcy, dcz, dpad;
-    int32_t chan_bytes;        // bytes of one storage channel
+    int32_t chan_bytes;        // bytes of one channel of the gather layout
     int32_t master_chan_bytes; // bytes of one FP32 channel
     int32_t storage;           // EXS_F32 / EXS_BF16 / EXS_F16
     int32_t pad3;
@@ -145,11 +145,14 @@ __host__ __device__ inline size_t dock_lds_bytes(int lpw, int top_k, int waves, 
 }
 constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 
-// Launchers (dock_kernels.hip).
+// Launchers (dock_misc.hip).
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
                        size_t lds, hipStream_t st);
-hipError_t launch_convert_grid(const float* src, uint32_t* dst, int64_t count, int nx, int storage,
-                               hipStream_t st);
+// Per-cell gather layout of a pocket channel (16-byte entries): FP32 quads over (nx-1)(ny-1)nz,
+// 16-bit octets over (nx-1)(ny-1)(nz-1).
+int64_t expanded_entries(int nx, int ny, int nz, int storage);
+hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,
+                              int storage, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 hipError_t upload_trig_tables();
 const void* dock_kernel_fn(int storage, int S, int ppl);
