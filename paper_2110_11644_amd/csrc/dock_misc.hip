@@ -29,29 +29,31 @@ __device__ __forceinline__ uint32_t to16(float v, int storage) {
 }
 
 // Expand the FP32 master [C][nz][ny][nx] (x fastest) into the per-cell gather layout, one
-// 16-byte entry per thread; entries of a channel are indexed (z * cy + y) * cx + x with
-// cx = nx-1, cy = ny-1.
-//  FP32 (storage 0): nz slices of quads {V(x,y,z), V(x+1,y,z), V(x,y+1,z), V(x+1,y+1,z)}.
-//  16-bit (1 BF16, 2 FP16): nz-1 slices of octets, dword j = corner(2j) | corner(2j+1) << 16,
-//  corner index dx + 2 dy + 4 dz.
+// 16-byte entry per thread.  Cells of a channel are indexed (z * cy + y) * cx + x with
+// cx = nx-1, cy = ny-1, cz = nz-1; corner index dx + 2 dy + 4 dz.
+//  FP32 (storage 0): two entries per cell, entry dz = {V(x,y,z+dz), V(x+1,y,z+dz),
+//  V(x,y+1,z+dz), V(x+1,y+1,z+dz)}.
+//  16-bit (1 BF16, 2 FP16): one entry per cell, dword j = corner(2j) | corner(2j+1) << 16.
 __global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restrict__ dst,
                                    int nx, int ny, int nz, int64_t per_chan, int64_t count,
                                    int storage) {
     const int cx = nx - 1, cy = ny - 1;
     const int64_t nxy = (int64_t)nx * ny, chan = nxy * nz;
+    const int per_cell = storage == 0 ? 2 : 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = i / per_chan, e = i - c * per_chan;
-        const int x = (int)(e % cx);
-        const int64_t yz = e / cx;
+        const int64_t cell = e / per_cell;
+        const int half = (int)(e - cell * per_cell);
+        const int x = (int)(cell % cx);
+        const int64_t yz = cell / cx;
         const int y = (int)(yz % cy), z = (int)(yz / cy);
         const float* b = src + c * chan + (int64_t)z * nxy + (int64_t)y * nx + x;
         uint4 o;
         if (storage == 0) {
-            o.x = __builtin_bit_cast(uint32_t, b[0]);
-            o.y = __builtin_bit_cast(uint32_t, b[1]);
-            o.z = __builtin_bit_cast(uint32_t, b[nx]);
-            o.w = __builtin_bit_cast(uint32_t, b[nx + 1]);
+            const float* q = b + half * nxy;
+            o = make_uint4(__builtin_bit_cast(uint32_t, q[0]), __builtin_bit_cast(uint32_t, q[1]),
+                           __builtin_bit_cast(uint32_t, q[nx]), __builtin_bit_cast(uint32_t, q[nx + 1]));
         } else {
             uint32_t w[4];
             for (int j = 0; j < 4; ++j) {
@@ -91,7 +93,7 @@ const void* dock_kernel_fn(int storage, int S, int ppl) {
 }
 
 int64_t expanded_entries(int nx, int ny, int nz, int storage) {
-    return (int64_t)(nx - 1) * (ny - 1) * (storage == 0 ? nz : nz - 1);
+    return (int64_t)(nx - 1) * (ny - 1) * (nz - 1) * (storage == 0 ? 2 : 1);
 }
 
 hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,

@@ -124,7 +124,7 @@ struct Pocket {
     int nx = 0, ny = 0, nz = 0, channels = 0, storage = EXS_F32;
     double h = 0, origin[3] = {0, 0, 0};
     float* master = nullptr;     // FP32 texels
-    void* tex = nullptr;         // per-cell gather layout (FP32 quads or 16-bit octets)
+    void* tex = nullptr;         // per-cell gather layout (8 corners per cell)
     GridDesc desc;
     std::atomic<int> users{0};
 };
@@ -281,7 +281,7 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         const int64_t chan = (int64_t)nx * ny * nz;
         const int64_t tex_chan_bytes = expanded_entries(nx, ny, nz, storage) * 16;
         if (tex_chan_bytes > INT32_MAX)
-            return fail(EXS_EINVAL, "a grid channel must expand to < 2 GiB (16 B per cell)");
+            return fail(EXS_EINVAL, "a grid channel must expand to < 2 GiB (32 B per FP32 cell, 16 B per 16-bit cell)");
         const int64_t count = chan * channels;
         if (!values_on_device) {
             for (int64_t i = 0; i < count; ++i)

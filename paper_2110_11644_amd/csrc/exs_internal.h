@@ -148,8 +148,8 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 // Launchers (dock_misc.hip).
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
                        size_t lds, hipStream_t st);
-// Per-cell gather layout of a pocket channel (16-byte entries): FP32 quads over (nx-1)(ny-1)nz,
-// 16-bit octets over (nx-1)(ny-1)(nz-1).
+// Per-cell gather layout of a pocket channel, in 16-byte entries: the 8 corners of each of the
+// (nx-1)(ny-1)(nz-1) cells, two entries per cell for FP32, one for 16-bit.
 int64_t expanded_entries(int nx, int ny, int nz, int storage);
 hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,
                               int storage, hipStream_t st);
