@@ -186,6 +186,27 @@ def test_multi_pocket_persistent_and_per_pocket_agree(B, oracle_lib):
     log("mixed stats", stats)
 
 
+@pytest.mark.parametrize("storage", [0, 1, 2], ids=["f32", "bf16", "f16"])
+def test_odd_unequal_grid_edges(B, oracle_lib, small, storage):
+    """A grid with odd, unequal edges (x 45, y 38, z 41 texels) cut from the small pocket, so
+    that the cell blocks at the odd edges are padding and many atoms fall outside the grid and
+    are clamped to its faces: each texel storage matches the oracle on the same grid (for
+    16-bit storage the oracle reads the grid rounded by numpy)."""
+    import types
+    O = oracle_lib
+    p, _, batch = small
+    vals = np.ascontiguousarray(p.values[:, :41, :38, :45])
+    cut = types.SimpleNamespace(values=vals, spacing=p.spacing, origin=p.origin)
+    ref_vals = vals if storage == 0 else (S.to_bf16_rne if storage == 1 else S.to_f16_rne)(vals)
+    g = O.Grid(ref_vals, p.spacing, p.origin)
+    s = S.SMALL.search
+    sub = batch.subset(range(12))
+    log("odd grid 45x38x41, storage %d" % storage)
+    out = run(B, [cut], sub, s, storage=storage)
+    stats = check_all(O, [g], O.Params.of(s), sub, out)
+    log("odd grid stats", stats)
+
+
 def test_invalid_requests_fail_alone(B, small):
     p, g, batch = small
     pid = B.exs_load_pocket_grid(p.values, p.spacing, p.origin)
