@@ -36,12 +36,13 @@ def progress(*a):
 
 
 def algorithmic_counts(binding, batch, search, channels):
-    """Per-ligand algorithmic work of the plain method: texel lookups L, pair tests Q and
-    rotated atoms Rot (one orientation each; multiply by K).
-      L = n + P * (sum_b (S-1) m_b + (T-1) n),  Q = c0 + P * sum_b (S-1) x_b,
+    """Per-ligand algorithmic work (one orientation each; multiply by K): texel lookups L,
+    pair tests Q and turned atom positions Rot.
+      L = n + P * (sum_b (S-1) m_b + (T-1) n),  Q = c0 + P * sum_b x_b,
       Rot = P * sum_b (S-1) m_b,
     m_b = atoms turning with bond b, x_b = non-excluded (moving, static) pairs, c0 = all
-    non-excluded pairs."""
+    non-excluded pairs.  A (moving, static) pair is tested once per bond: its distance over
+    all S turns is one closed form (the clashing turns form one arc)."""
     S_, P, T = search.torsion_steps, search.passes, search.n_offsets
     L = np.zeros(batch.n_ligands); Q = np.zeros(batch.n_ligands); R = np.zeros(batch.n_ligands)
     for l in range(batch.n_ligands):
@@ -58,7 +59,7 @@ def algorithmic_counts(binding, batch, search, channels):
             m = int(mv.sum())
             x = int(((~ex[mv])[:, ~mv]).sum())
             lk += P * (S_ - 1) * m
-            q += P * (S_ - 1) * x
+            q += P * x
             rot += P * (S_ - 1) * m
         L[l], Q[l], R[l] = lk, q, rot
     return L, Q, R
@@ -111,7 +112,7 @@ def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1):
     scale = batch.n_ligands / sub.n_ligands
     K = search.n_orient
     tex_bytes = 8.0 * (4.0 if storage == 0 else 2.0) * K * Lk.sum() * scale
-    ops = K * (30.0 * Lk.sum() + 7.0 * Qk.sum() + 15.0 * Rk.sum()) * scale
+    ops = K * (30.0 * Lk.sum() + 14.0 * Qk.sum() + 6.0 * Rk.sum()) * scale
     gbs = tex_bytes / (kernel_ms * 1e-3) / 1e9
     tops = ops / (kernel_ms * 1e-3) / 1e12
     mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
