@@ -103,9 +103,10 @@ def cpu_baseline(workload, pocket, batch, search, max_ligands=1024, budget_s=20.
                       "FP64 oracle, OpenMP over ligands, %.1f s" % (done, workload, dt)}
 
 
-def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1):
+def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1, traffic=None):
     """Roofline objects (texel bytes vs HBM peak, FP32 lane-ops vs VALU peak) of one launch over
-    `batch`; the algorithmic counts come from every `sample_every`-th ligand, scaled."""
+    `batch`; the algorithmic counts come from every `sample_every`-th ligand, scaled.
+    `traffic`: measured HBM bytes of the launch, if known."""
     idx = list(range(0, batch.n_ligands, sample_every))
     sub = batch if sample_every == 1 else batch.subset(idx)
     Lk, Qk, Rk = algorithmic_counts(B, sub, search, channels)
@@ -116,9 +117,9 @@ def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1):
     gbs = tex_bytes / (kernel_ms * 1e-3) / 1e9
     tops = ops / (kernel_ms * 1e-3) / 1e12
     mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     alu = {"bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS,
-           "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None}
+           "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": traffic}
     roof, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
     roof = dict(roof)
     roof["kernel"] = "exs::dock_kernel"
@@ -489,7 +490,11 @@ def main():
     stream = torch.cuda.current_stream()
     storage = B.STORAGE[args.storage]
     pid = B.exs_load_pocket_grid(pocket.values, pocket.spacing, pocket.origin, storage, stream=stream)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     bid = B.exs_upload_ligands(batch, pocket_ids=[pid], stream=stream)
+    torch.cuda.synchronize()
+    upload_s = time.perf_counter() - t_up
     flags = B.EXS_FLAG_PERSISTENT if args.persistent else 0
     prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                           s.clash_cutoff, s.clash_penalty, top_k=0, poses_per_lane=args.ppl,
@@ -520,26 +525,10 @@ def main():
 
     # roofline of the dock kernel: algorithmic texel bytes and FP32 lane-ops per launch
     progress("counting algorithmic work")
-    Lk, Qk, Rk = algorithmic_counts(B, batch, s, pocket.channels)
-    K = s.n_orient
-    tex_bytes = 8.0 * 4.0 * K * Lk.sum() * (0.5 if storage else 1.0)
-    ops = K * (30.0 * Lk.sum() + 7.0 * Qk.sum() + 15.0 * Rk.sum())
     kms = float(np.mean(kernel_ms))
-    gbs = tex_bytes / (kms * 1e-3) / 1e9
-    tops = ops / (kms * 1e-3) / 1e12
-    mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    alu = {"bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-           "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None}
     traffic = measured_traffic(L) if (args.workload == "scale" and storage == 0 and args.ppl in (0, 1)
                                       and args.lpw in (0, 1) and not args.persistent) else None
-    mem["traffic"] = traffic
-    alu["traffic"] = traffic
-    roof, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
-    roof = dict(roof)
-    roof["kernel"] = "exs::dock_kernel"
-    roof["kernel_ms"] = round(kms, 3)
-    roof["other"] = other
+    roof = roofline_of(B, batch, s, pocket.channels, kms, storage, traffic=traffic)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -565,13 +554,16 @@ def main():
             "workload": "%s: %d ligands x 1 pocket %d^3 x %d ch at %.3f A (%s texels); K=%d "
                         "orientations, S=%d torsion steps, P=%d passes, T=%d offsets; %s" % (
                             wl.name, L, pocket.n, pocket.channels, pocket.spacing, args.storage,
-                            K, s.torsion_steps, s.passes, s.n_offsets,
+                            s.n_orient, s.torsion_steps, s.passes, s.n_offsets,
                             "one persistent launch" if args.persistent else "one launch per pocket"),
             "ligands": L, "atoms": A, "parallelism": "single GPU",
             "poses_per_lane": args.ppl, "ligands_per_wg": args.lpw,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        # not the value: the same steps with the host-side ligand upload (packing + PCIe) added
+        "host_inclusive": {"upload_ms": round(upload_s * 1e3, 2),
+                           "docks_per_s": round(L / (upload_s + dt / args.steps), 2)},
     }
     print(json.dumps(line), flush=True)
 

@@ -70,14 +70,15 @@ const char* exs_last_error(void);
  *               centre, where each ligand's centroid is placed.
  *   storage     EXS_F32, EXS_BF16 or EXS_F16: texels are stored in this type
  *               (round to nearest even); interpolation and accumulation run in
- *               FP32.  16-bit texels are kept as packed x-neighbour pairs (one
- *               4-byte word per texel holds it and its +x neighbour), so a
- *               corner pair is one 4-byte gather instead of the 8 bytes of FP32.
- *               The FP32 master copy is always kept as well: it feeds the FP64
- *               rescoring of the top poses.
+ *               FP32.  The search reads a copy expanded per cell: the 8
+ *               corners of every cell together (32 B FP32, 16 B 16-bit), so a
+ *               lookup is one contiguous block; this costs 8x (FP32) or 4x
+ *               (16-bit) the bytes of the input, and each channel's expanded
+ *               copy must stay below 2 GiB.  The FP32 master copy is always
+ *               kept as well: it feeds the FP64 rescoring of the top poses.
  *   pocket_id_out  receives the handle.
  * Errors: EXS_EINVAL (bad sizes, channels > EXS_MAX_CHANNELS, non-finite
- * texels), EXS_ENOMEM, EXS_EDEVICE.
+ * texels, an expanded channel of 2 GiB or more), EXS_ENOMEM, EXS_EDEVICE.
  */
 int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channels,
                          double spacing_A, const double origin_A[3], int storage,
