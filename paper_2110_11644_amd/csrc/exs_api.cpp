@@ -545,7 +545,11 @@ int exs_release_ligands(int64_t batch) {
 
 namespace {
 
-// Longest-first processing order, grouped by pocket for per-pocket launches.
+// Processing order.  Per-pocket launches: grouped by pocket, longest first in each group.
+// Persistent launch: pocket-major, cut into kXcds contiguous queues of equal cost, each
+// sorted longest first; queue q (run first by the workgroups of XCD q) then touches few
+// pockets, so each XCD's L2 holds few grids.  The device array holds the order followed
+// by the kXcds + 1 queue bounds.
 int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_t st,
                 int32_t** d_order, std::vector<int>* groups) {
     std::vector<int> key = {K, S, P, T, persistent};
@@ -564,21 +568,34 @@ int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_
     std::vector<int> ord(b.L);
     std::iota(ord.begin(), ord.end(), 0);
     const int n_slots = (int)b.pockets.size();
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+        if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
+        return cost[a] > cost[c];
+    });
     if (persistent) {
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+        double total = 0.0;
+        for (int l = 0; l < b.L; ++l) total += cost[l];
+        std::vector<int32_t> bounds(kXcds + 1, b.L);
+        bounds[0] = 0;
+        double acc = 0.0;
+        int q = 1;
+        for (int i = 0; i < b.L && q < kXcds; ++i) {
+            acc += cost[ord[i]];
+            while (q < kXcds && acc >= total * q / kXcds) bounds[q++] = i + 1;
+        }
+        for (int qq = 0; qq < kXcds; ++qq)
+            std::stable_sort(ord.begin() + bounds[qq], ord.begin() + bounds[qq + 1],
+                             [&](int a, int c) { return cost[a] > cost[c]; });
+        ord.insert(ord.end(), bounds.begin(), bounds.end());
         groups->assign(1, b.L);
     } else {
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
-            if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
-            return cost[a] > cost[c];
-        });
         groups->assign(n_slots, 0);
         for (int l = 0; l < b.L; ++l) (*groups)[b.info[l].pocket]++;
     }
     int32_t* d = nullptr;
-    HIP_TRY(hipMalloc(&d, std::max(1, b.L) * sizeof(int32_t)));
-    if (b.L > 0) {
-        HIP_TRY(hipMemcpyAsync(d, ord.data(), b.L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMalloc(&d, std::max<size_t>(1, ord.size()) * sizeof(int32_t)));
+    if (!ord.empty()) {
+        HIP_TRY(hipMemcpyAsync(d, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
     b.d_orders[key] = d;
@@ -674,7 +691,9 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         a.n_order = b.L;
         a.n_tiles = (b.L + a.lpw - 1) / a.lpw;
         a.persistent = 1;
-        hipError_t e = launch_zero_ints(a.tile_counter, 1, st);
+        a.queue_bounds = d_order + b.L;
+        a.n_queues = kXcds;
+        hipError_t e = launch_zero_ints(a.tile_counter, kXcds, st);
         if (e != hipSuccess) return e;
         return launch_dock(a, storage, ppl, resident, threads, lds, st);
     }
@@ -834,7 +853,7 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 (rc = job_alloc(al, &a.topk_score64, (size_t)L * top_k)) ||
                 (rc = job_alloc(al, &a.topk_theta, (size_t)R * top_k)) ||
                 (rc = job_alloc(al, &a.topk_tau, (size_t)L * top_k)) ||
-                (rc = job_alloc(al, &a.tile_counter, (size_t)1)) ||
+                (rc = job_alloc(al, &a.tile_counter, (size_t)kXcds)) ||
                 (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
                 free_allocs(al);
                 return rc;

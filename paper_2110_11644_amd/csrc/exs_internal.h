@@ -13,6 +13,7 @@ constexpr int kMaxTopK = 32;
 constexpr int kMaxLpw = 8;       // ligands per workgroup
 constexpr int kMaxWavesPerWg = 8;
 constexpr int kMaxThreadsPerWg = kMaxWavesPerWg * kWave;
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 
 // Turn tables: for S in {8, 16, 32}, cos then sin of 2*pi*s/S at offset trig_offset(S).
 constexpr int kTrigEntries = 2 * (8 + 16 + 32);
@@ -105,7 +106,13 @@ struct DockArgs {
     // per-workgroup-slot scratch of pose coordinates: [lpw][n_max][3][kp] floats
     float* scratch;
     int64_t slot_floats;
-    int32_t* tile_counter;    // persistent launches: next tile to take
+    int32_t* tile_counter;    // persistent launches: next tile of each queue [n_queues]
+    // persistent launches: n_queues + 1 positions in `order`, queue q = [qb[q], qb[q+1]);
+    // a workgroup takes tiles from the queue of its XCD first, then from the others.
+    // Null: one queue over the whole order.
+    const int32_t* queue_bounds;
+    int32_t n_queues;
+    int32_t pad1;
     // outputs (indexed by caller ligand / rotatable-bond index)
     float* orient_score;      // [L*K]
     uint8_t* orient_theta;    // [R*K], element (rot_base+b)*K + k
