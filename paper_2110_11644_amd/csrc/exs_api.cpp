@@ -568,27 +568,17 @@ int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_
     std::vector<int> ord(b.L);
     std::iota(ord.begin(), ord.end(), 0);
     const int n_slots = (int)b.pockets.size();
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
-        if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
-        return cost[a] > cost[c];
-    });
     if (persistent) {
-        double total = 0.0;
-        for (int l = 0; l < b.L; ++l) total += cost[l];
-        std::vector<int32_t> bounds(kXcds + 1, b.L);
-        bounds[0] = 0;
-        double acc = 0.0;
-        int q = 1;
-        for (int i = 0; i < b.L && q < kXcds; ++i) {
-            acc += cost[ord[i]];
-            while (q < kXcds && acc >= total * q / kXcds) bounds[q++] = i + 1;
-        }
-        for (int qq = 0; qq < kXcds; ++qq)
-            std::stable_sort(ord.begin() + bounds[qq], ord.begin() + bounds[qq + 1],
-                             [&](int a, int c) { return cost[a] > cost[c]; });
-        ord.insert(ord.end(), bounds.begin(), bounds.end());
+        std::vector<int> pocket(b.L);
+        for (int l = 0; l < b.L; ++l) pocket[l] = b.info[l].pocket;
+        ord.resize(b.L + kXcds + 1);
+        xcd_queues(b.L, pocket.data(), cost.data(), kXcds, ord.data(), ord.data() + b.L);
         groups->assign(1, b.L);
     } else {
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+            if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
+            return cost[a] > cost[c];
+        });
         groups->assign(n_slots, 0);
         for (int l = 0; l < b.L; ++l) (*groups)[b.info[l].pocket]++;
     }

@@ -7,6 +7,8 @@
 // (1-2, 1-3, 1-4) are excluded from the clash term.
 #include "exs_pack.h"
 
+#include <algorithm>
+
 #include <stdio.h>
 
 #include "exs.h"
@@ -143,6 +145,30 @@ double ligand_cost(int n, const int16_t* m, int nrot, int K, int S, int P, int T
     }
     look += (double)P * (T > 1 ? T : 0) * n;
     return (double)K * (look * 40.0 + pairs * 20.0);
+}
+
+void xcd_queues(int n, const int* pocket, const double* cost, int n_queues, int32_t* order,
+                int32_t* bounds) {
+    std::vector<int32_t> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+        if (pocket[a] != pocket[c]) return pocket[a] < pocket[c];
+        return cost[a] > cost[c];
+    });
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) total += cost[i];
+    for (int q = 0; q <= n_queues; ++q) bounds[q] = n;
+    bounds[0] = 0;
+    double acc = 0.0;
+    int q = 1;
+    for (int i = 0; i < n && q < n_queues; ++i) {
+        acc += cost[ord[i]];
+        while (q < n_queues && acc >= total * q / n_queues) bounds[q++] = i + 1;
+    }
+    for (int r = 0; r < n_queues; ++r)
+        std::stable_sort(ord.begin() + bounds[r], ord.begin() + bounds[r + 1],
+                         [&](int a, int c) { return cost[a] > cost[c]; });
+    std::copy(ord.begin(), ord.end(), order);
 }
 
 }  // namespace exs

@@ -297,11 +297,12 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
         Iteration& it = it_[i];
         SRV_TRY(hipStreamCreateWithFlags(&it.stream, hipStreamNonBlocking));
         SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
-        if ((rc = dev_alloc(dev_bufs_, &it.d_order, max_iter_)) ||
-            (rc = dev_alloc(dev_bufs_, &it.d_counter, 1)) ||
+        if ((rc = dev_alloc(dev_bufs_, &it.d_order, max_iter_ + kXcds + 1)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_counter, kXcds)) ||
             (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)))
             return rc;
-        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * max_iter_, hipHostMallocDefault));
+        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (max_iter_ + kXcds + 1),
+                              hipHostMallocDefault));
     }
     pocket_ids_.assign(pockets, pockets + n_pockets);
     for (int32_t id : pocket_ids_) rt::pocket_use(id, +1);
@@ -416,30 +417,40 @@ bool Server::admit_locked() {
 
 bool Server::launch(Iteration& it) {
     // oldest requests first, up to max_iter_ ligands
-    std::vector<std::pair<double, int32_t>> list;
+    std::vector<double> cost;
+    std::vector<int> pocket;
+    std::vector<int32_t> lig;
     it.work.clear();
     for (Request* r : inflight_) {
-        if ((int)list.size() >= max_iter_) break;
-        int take = std::min(r->L - r->scheduled, max_iter_ - (int)list.size());
+        if ((int)lig.size() >= max_iter_) break;
+        int take = std::min(r->L - r->scheduled, max_iter_ - (int)lig.size());
         if (take <= 0) continue;
-        for (int i = 0; i < take; ++i)
-            list.emplace_back(r->cost[r->scheduled + i], r->lig0 + r->scheduled + i);
+        for (int i = 0; i < take; ++i) {
+            cost.push_back(r->cost[r->scheduled + i]);
+            pocket.push_back(r->info[r->scheduled + i].pocket);
+            lig.push_back(r->lig0 + r->scheduled + i);
+        }
         r->scheduled += take;
         it.work.emplace_back(r, take);
     }
-    if (list.empty()) return false;
-    std::stable_sort(list.begin(), list.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-    for (size_t i = 0; i < list.size(); ++i) it.h_order[i] = list[i].second;
+    if (lig.empty()) return false;
+    // per-XCD queues (pocket-major, equal cost, longest first), bounds after the order
+    const int n = (int)lig.size();
+    std::vector<int32_t> ord(n);
+    xcd_queues(n, pocket.data(), cost.data(), kXcds, ord.data(), it.h_order + n);
+    for (int i = 0; i < n; ++i) it.h_order[i] = lig[ord[i]];
     if (up_pending_) (void)hipStreamWaitEvent(it.stream, up_event_, 0);
     DockArgs a = base_;
     a.order = it.d_order;
-    a.n_order = (int)list.size();
+    a.n_order = n;
     a.n_tiles = (a.n_order + lpw_ - 1) / lpw_;
     a.tile_counter = it.d_counter;
+    a.queue_bounds = it.d_order + n;
+    a.n_queues = kXcds;
     a.scratch = it.scratch;
-    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * list.size(),
+    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (n + kXcds + 1),
                                   hipMemcpyHostToDevice, it.stream);
-    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, 1, it.stream);
+    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, kXcds, it.stream);
     if (e == hipSuccess)
         e = launch_dock(a, storage_, ppl_, std::min(resident_, a.n_tiles), threads_, lds_, it.stream);
     if (e == hipSuccess) e = hipEventRecord(it.done, it.stream);
