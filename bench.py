@@ -130,6 +130,33 @@ def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1, 
     return roof
 
 
+def gather_probe(B, pid, storage, stream, batch, search, channels, kernel_ms,
+                 lanes=256 * 1024, per_lane=256):
+    """Lookup rate of the texel-gather probe (the docking lookup alone, independent random
+    points) on the same pocket, for two footprints: a 6 A cube around the centre (its texel
+    blocks fit an XCD's L2) and a 20 A cube (pocket-wide, beyond L2); the best of 8 or 16
+    lookups in flight per lane.  Beside it the dock kernel's own lookup rate."""
+    sub = batch.subset(range(0, batch.n_ligands, 10))
+    Lk, _, _ = algorithmic_counts(B, sub, search, channels)
+    dock_lookups = search.n_orient * Lk.sum() * batch.n_ligands / sub.n_ligands
+    out = {"lookups_per_launch": lanes * per_lane,
+           "texel_bytes_per_lookup": 32 if storage == 0 else 16}
+    for name, half in (("cube_6A", 3.0), ("cube_20A", 10.0)):
+        best = None
+        for nb in (8, 16):
+            B.exs_gather_probe(pid, lanes, per_lane, half, 0.0, 7, batch=nb, stream=stream)   # warm
+            ms, _ = B.exs_gather_probe(pid, lanes, per_lane, half, 0.0, 11, batch=nb, stream=stream)
+            rate = lanes * per_lane / (ms * 1e-3)
+            if best is None or rate > best[1]:
+                best = (ms, rate, nb)
+        out[name] = {"ms": round(best[0], 3), "lookups_per_s": round(best[1], 0), "in_flight": best[2]}
+    out["dock_lookups_per_s"] = round(dock_lookups / (kernel_ms * 1e-3), 0)
+    out["dock_frac_of_cube_6A"] = round(out["dock_lookups_per_s"] / out["cube_6A"]["lookups_per_s"], 3)
+    out["dock_frac_of_cube_20A"] = round(out["dock_lookups_per_s"] / out["cube_20A"]["lookups_per_s"], 3)
+    progress("gather probe: %s" % out)
+    return out
+
+
 def load_batched_pockets(S, B, storage, stream, log=True, pockets=None):
     wl = S.BATCHED
     if pockets is None:
@@ -529,6 +556,7 @@ def main():
     traffic = measured_traffic(L) if (args.workload == "scale" and storage == 0 and args.ppl in (0, 1)
                                       and args.lpw in (0, 1) and not args.persistent) else None
     roof = roofline_of(B, batch, s, pocket.channels, kms, storage, traffic=traffic)
+    probe = gather_probe(B, pid, storage, stream, batch, s, pocket.channels, kms)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -561,6 +589,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "gather_probe": probe,
         # not the value: the same steps with the host-side ligand upload (packing + PCIe) added
         "host_inclusive": {"upload_ms": round(upload_s * 1e3, 2),
                            "docks_per_s": round(L / (upload_s + dt / args.steps), 2)},

@@ -84,6 +84,25 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
                          double spacing_A, const double origin_A[3], int storage,
                          int values_on_device, void* stream, int32_t* pocket_id_out);
 
+/*
+ * Gather probe: the docking kernels' texel lookup (same per-cell blocks, loads and FP32
+ * trilinear arithmetic) alone, to measure the lookup rate the search is held against
+ * (Sec. 3.1: the score of a pose is a lookup per atom in the pocket's grids).
+ * n_lanes lanes (rounded up to a multiple of 256) each do lookups_per_lane lookups (rounded
+ * up to a multiple of batch), issued `batch` (8, 16 or 32) at a time independently of each
+ * other, at 4, 3 or 2 waves per SIMD respectively, at
+ * pseudo-random points of the cube of half edge half_edge_A (A) around the pocket centre:
+ * independent points when walk_step_A = 0, else a walk of at most walk_step_A per axis and
+ * step, clamped to the cube.  Channels cycle per lookup.  Runs on `stream` and waits for it.
+ *   ms_out        device time of the probe kernel (HIP events).
+ *   checksum_out  sum of the lanes' lookup sums (may be NULL).
+ * Errors: EXS_EINVAL (sizes, batch, non-finite or negative lengths, pocket on another device),
+ * EXS_ENOENT (unknown pocket), EXS_ENOMEM, EXS_EDEVICE.
+ */
+int exs_gather_probe(int32_t pocket_id, int64_t n_lanes, int lookups_per_lane, int batch,
+                     float half_edge_A, float walk_step_A, uint32_t seed, void* stream,
+                     float* ms_out, double* checksum_out);
+
 /* Free a pocket's device grids.  Jobs still using it must be released first. */
 int exs_unload_pocket(int32_t pocket_id);
 

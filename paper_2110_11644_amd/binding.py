@@ -26,7 +26,7 @@ STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
 # exported symbols (kept in step with include/exs.h)
 SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
            "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
-           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job",
+           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
            "exs_server_destroy")
 
@@ -95,6 +95,8 @@ def lib():
         L.exs_get_orientation_results.argtypes = [i64, vp, vp]
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
+        L.exs_gather_probe.argtypes = [i32, i64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_uint32, vp,
+                                       C.POINTER(C.c_float), C.POINTER(C.c_double)]
         L.exs_server_create.argtypes = [vp, C.c_int, C.POINTER(exs_search_params),
                                         C.POINTER(exs_server_config), C.POINTER(i64)]
         L.exs_server_submit.argtypes = [i64, C.POINTER(exs_ligand_batch), C.POINTER(i64)]
@@ -249,6 +251,17 @@ def exs_job_elapsed_ms(job: int) -> float:
 
 def exs_release_job(job: int):
     _check(lib().exs_release_job(int(job)))
+
+
+def exs_gather_probe(pocket_id: int, n_lanes: int, lookups_per_lane: int, half_edge_A: float,
+                     walk_step_A: float = 0.0, seed: int = 1, batch: int = 16, stream=None):
+    """Device time (ms) and checksum of the texel-gather probe on a loaded pocket."""
+    ms = C.c_float()
+    chk = C.c_double()
+    _check(lib().exs_gather_probe(int(pocket_id), int(n_lanes), int(lookups_per_lane), int(batch),
+                                  float(half_edge_A), float(walk_step_A), int(seed) & 0xffffffff,
+                                  _stream(stream), C.byref(ms), C.byref(chk)))
+    return float(ms.value), float(chk.value)
 
 
 def exs_server_create(pocket_ids, params: exs_search_params, hbm_budget_bytes: int = 0,

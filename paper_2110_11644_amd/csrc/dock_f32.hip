@@ -1,5 +1,6 @@
 // Instantiates the dock kernel for FP32 texels.
 #include "dock_kernels.inc"
+#include "gather_probe.inc"
 
 namespace exs {
 
@@ -21,6 +22,18 @@ const void* dock_kernel_fn_f32(int S, int ppl) {
     EXS_FN(8, 1) EXS_FN(8, 2) EXS_FN(16, 1) EXS_FN(16, 2) EXS_FN(32, 1) EXS_FN(32, 2)
 #undef EXS_FN
     return nullptr;
+}
+
+hipError_t launch_gather_probe_f32(const GridDesc* gd, int nb, int64_t blocks, int per_lane,
+                                float half, float walk, uint32_t seed, float* out, hipStream_t st) {
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (nb) {
+        case 8: hipLaunchKernelGGL((gather_probe_kernel<TexF32, 8>), grid, block, 0, st, gd, per_lane, half, walk, seed, out); break;
+        case 16: hipLaunchKernelGGL((gather_probe_kernel<TexF32, 16>), grid, block, 0, st, gd, per_lane, half, walk, seed, out); break;
+        case 32: hipLaunchKernelGGL((gather_probe_kernel<TexF32, 32>), grid, block, 0, st, gd, per_lane, half, walk, seed, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t upload_trig_f32(const float* t32, const double* t64) {

@@ -15,6 +15,12 @@ const void* dock_kernel_fn_f16(int S, int ppl);
 hipError_t upload_trig_f32(const float* t32, const double* t64);
 hipError_t upload_trig_bf16(const float* t32, const double* t64);
 hipError_t upload_trig_f16(const float* t32, const double* t64);
+hipError_t launch_gather_probe_f32(const GridDesc* gd, int nb, int64_t blocks, int per_lane,
+                                   float half, float walk, uint32_t seed, float* out, hipStream_t st);
+hipError_t launch_gather_probe_bf16(const GridDesc* gd, int nb, int64_t blocks, int per_lane,
+                                   float half, float walk, uint32_t seed, float* out, hipStream_t st);
+hipError_t launch_gather_probe_f16(const GridDesc* gd, int nb, int64_t blocks, int per_lane,
+                                   float half, float walk, uint32_t seed, float* out, hipStream_t st);
 
 
 
@@ -79,6 +85,16 @@ hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, in
         case 0: return launch_dock_f32(a, ppl, grid, block, lds, st);
         case 1: return launch_dock_bf16(a, ppl, grid, block, lds, st);
         case 2: return launch_dock_f16(a, ppl, grid, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gather_probe(const GridDesc* gd, int storage, int nb, int64_t blocks, int per_lane,
+                               float half, float walk, uint32_t seed, float* out, hipStream_t st) {
+    switch (storage) {
+        case 0: return launch_gather_probe_f32(gd, nb, blocks, per_lane, half, walk, seed, out, st);
+        case 1: return launch_gather_probe_bf16(gd, nb, blocks, per_lane, half, walk, seed, out, st);
+        case 2: return launch_gather_probe_f16(gd, nb, blocks, per_lane, half, walk, seed, out, st);
         default: return hipErrorInvalidValue;
     }
 }

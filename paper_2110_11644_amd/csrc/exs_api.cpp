@@ -994,6 +994,68 @@ int exs_job_elapsed_ms(int64_t job, float* ms) {
     return EXS_OK;
 }
 
+int exs_gather_probe(int32_t pocket_id, int64_t n_lanes, int lookups_per_lane, int batch,
+                     float half_edge_A, float walk_step_A, uint32_t seed, void* stream,
+                     float* ms_out, double* checksum_out) {
+    try {
+        if (!ms_out) return fail(EXS_EINVAL, "null argument");
+        if (batch != 8 && batch != 16 && batch != 32) return fail(EXS_EINVAL, "batch %d is not 8, 16 or 32", batch);
+        if (n_lanes < 1 || n_lanes > ((int64_t)1 << 30))
+            return fail(EXS_EINVAL, "n_lanes %lld outside [1, 2^30]", (long long)n_lanes);
+        if (lookups_per_lane < 1 || lookups_per_lane > (1 << 20))
+            return fail(EXS_EINVAL, "lookups_per_lane %d outside [1, 2^20]", lookups_per_lane);
+        if (!(half_edge_A >= 0.0f) || !isfinite(half_edge_A) || !(walk_step_A >= 0.0f) || !isfinite(walk_step_A))
+            return fail(EXS_EINVAL, "half edge and walk step must be finite and >= 0");
+        std::shared_ptr<Pocket> pk;
+        {
+            std::lock_guard<std::mutex> lk(g_reg_mu);
+            auto it = g_pockets.find(pocket_id);
+            if (it == g_pockets.end()) return fail(EXS_ENOENT, "unknown pocket %d", pocket_id);
+            pk = it->second;
+        }
+        int dev;
+        if (int rc = current_device(&dev)) return rc;
+        if (dev != pk->device) return fail(EXS_EINVAL, "pocket %d is on device %d", pocket_id, pk->device);
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t blocks = (n_lanes + 255) / 256;
+        const float inv_h = (float)(1.0 / pk->h);
+        GridDesc* d_gd = nullptr;
+        float* d_out = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&]() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (d_gd) (void)hipFree(d_gd);
+            if (d_out) (void)hipFree(d_out);
+        };
+        hipError_t e = hipMalloc(&d_gd, sizeof(GridDesc));
+        if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)blocks * 256 * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpyAsync(d_gd, &pk->desc, sizeof(GridDesc), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess)
+            e = launch_gather_probe(d_gd, pk->storage, batch, blocks, lookups_per_lane, half_edge_A * inv_h,
+                                    walk_step_A * inv_h, seed, d_out, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms_out, e0, e1);
+        if (e == hipSuccess && checksum_out) {
+            std::vector<float> h((size_t)blocks * 256);
+            e = hipMemcpy(h.data(), d_out, h.size() * sizeof(float), hipMemcpyDeviceToHost);
+            double sum = 0.0;
+            for (float v : h) sum += v;
+            *checksum_out = sum;
+        }
+        cleanup();
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? EXS_ENOMEM : EXS_EDEVICE, "gather probe: %s", hipGetErrorString(e));
+        return EXS_OK;
+    } catch (const std::exception& ex) {
+        return fail(EXS_ENOMEM, "exception: %s", ex.what());
+    }
+}
+
 int exs_release_job(int64_t job) {
     std::shared_ptr<Job> j;
     {

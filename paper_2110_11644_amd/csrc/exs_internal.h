@@ -160,6 +160,10 @@ hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, in
 int64_t expanded_entries(int nx, int ny, int nz, int storage);
 hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,
                               int storage, hipStream_t st);
+// Gather probe over the pocket `gd` (device pointer) in `storage`: blocks x 256 lanes, nb
+// (8, 16 or 32) independent lookups per round.
+hipError_t launch_gather_probe(const GridDesc* gd, int storage, int nb, int64_t blocks, int per_lane,
+                               float half, float walk, uint32_t seed, float* out, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 hipError_t upload_trig_tables();
 const void* dock_kernel_fn(int storage, int S, int ppl);
