@@ -353,8 +353,9 @@ def run_serving(args, torch, S, B):
                                int(cap_batch.atom_offset[-1]), 2, 1, stream)
     B.exs_release_ligands(cid)
     capacity = cap_batch.n_ligands / (cap_ms * 1e-3)
-    warm = max(10, args.requests // 20)
+    warm = max(10, args.requests // 20)   # 100 for the default 2,000 timed requests
     n_req = args.requests + warm
+    sweep = [float(x) for x in args.sweep.split(",") if x.strip()] if args.sweep else []
     mean_size = 82.0
     rate = args.load * capacity / mean_size
     trace = S.make_trace(n_req, rate)
@@ -368,8 +369,9 @@ def run_serving(args, torch, S, B):
         reqs.append(b)
     progress("generated %d ligands" % sum(b.n_ligands for b in reqs))
 
-    def replay(submit, finish):
-        """Submit at the trace's arrival times; returns per-request latency (s) and span."""
+    def replay(submit, finish, time_scale=1.0):
+        """Submit at the trace's arrival times (scaled by time_scale); returns per-request
+        latency (s) and span."""
         lat = [None] * n_req
         done_t = [None] * n_req
         handles = [None] * n_req
@@ -381,24 +383,42 @@ def run_serving(args, torch, S, B):
                 ready[i].wait()
                 finish(handles[i], reqs[i])
                 done_t[i] = time.perf_counter()
-                lat[i] = done_t[i] - (t0 + trace[i].arrival_s)
+                lat[i] = done_t[i] - (t0 + trace[i].arrival_s * time_scale)
         th = threading.Thread(target=waiter)
         th.start()
         for i, r in enumerate(trace):
             now = time.perf_counter() - t0
-            if r.arrival_s > now:
-                time.sleep(r.arrival_s - now)
+            if r.arrival_s * time_scale > now:
+                time.sleep(r.arrival_s * time_scale - now)
             handles[i] = submit(reqs[i])
             ready[i].set()
         th.join()
         return np.array(lat), t0, done_t
 
-    srv = B.exs_server_create(pids, prm, hbm_budget_bytes=8 << 30)
-    lat_s, t0s, done_s = replay(
-        lambda b: B.exs_server_submit(srv, b, pocket_ids=pids),
-        lambda h, b: B.exs_server_poll(srv, h, b.n_ligands, int(b.atom_offset[-1])))
-    stats = B.exs_server_get_stats(srv)
-    B.exs_server_destroy(srv)
+    timed_lig = sum(reqs[i].n_ligands for i in range(warm, n_req))
+
+    def serve(load):
+        """The trace at `load` (arrival times scaled) through a fresh server."""
+        scale = args.load / load
+        srv = B.exs_server_create(pids, prm, hbm_budget_bytes=8 << 30)
+        lat, t0, done = replay(
+            lambda b: B.exs_server_submit(srv, b, pocket_ids=pids),
+            lambda h, b: B.exs_server_poll(srv, h, b.n_ligands, int(b.atom_offset[-1])),
+            time_scale=scale)
+        st = B.exs_server_get_stats(srv)
+        B.exs_server_destroy(srv)
+        span = done[-1] - (t0 + trace[warm].arrival_s * scale)
+        return lat, span, st
+
+    lat_s, span_s, stats = serve(args.load)
+    swept = {}
+    for ld in sweep:
+        lat_x, span_x, st_x = serve(ld)
+        swept["%.2f" % ld] = {"p50_ms": round(float(np.percentile(lat_x[warm:], 50)) * 1e3, 2),
+                              "p99_ms": round(float(np.percentile(lat_x[warm:], 99)) * 1e3, 2),
+                              "docks_per_s": round(timed_lig / span_x, 1),
+                              "iterations": st_x["iterations"]}
+        progress("served at load %.2f: %s" % (ld, swept["%.2f" % ld]))
     progress("served: p50 %.1f ms p99 %.1f ms" % (np.percentile(lat_s[warm:], 50) * 1e3,
                                                  np.percentile(lat_s[warm:], 99) * 1e3))
     # plain per-request launch: one upload + dock + fetch per request, in arrival order
@@ -436,8 +456,6 @@ def run_serving(args, torch, S, B):
     wk.join()
     for pid in pids:
         B.exs_unload_pocket(pid)
-    timed_lig = sum(reqs[i].n_ligands for i in range(warm, n_req))
-    span_s = done_s[-1] - (t0s + trace[warm].arrival_s)
     span_p = done_p[-1] - (t0p + trace[warm].arrival_s)
     line = {
         "metric": "ligand-pocket docks/sec on 1 MI355X (served), p50/p99 latency",
@@ -453,6 +471,7 @@ def run_serving(args, torch, S, B):
         "served": {"p50_ms": round(float(np.percentile(lat_s[warm:], 50)) * 1e3, 2),
                    "p99_ms": round(float(np.percentile(lat_s[warm:], 99)) * 1e3, 2),
                    "docks_per_s": round(timed_lig / span_s, 1), "iterations": stats["iterations"]},
+        "served_other_loads": swept,
         "plain_per_request": {"p50_ms": round(float(np.percentile(lat_p[warm:], 50)) * 1e3, 2),
                               "p99_ms": round(float(np.percentile(lat_p[warm:], 99)) * 1e3, 2),
                               "docks_per_s": round(timed_lig / span_p, 1)},
@@ -469,7 +488,8 @@ def main():
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "small", "batched", "precision", "serving"])
     ap.add_argument("--tune", action="store_true", help="autotune the tile (batched)")
-    ap.add_argument("--requests", type=int, default=600, help="serving: timed requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: timed requests")
+    ap.add_argument("--sweep", default="0.5,0.9", help="serving: other offered loads to serve")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--oracle-sample", type=int, default=192,
                     help="precision: ligands checked against the FP64 oracle")

@@ -15,20 +15,26 @@
 
 namespace exs {
 
-static Bits128 flood(const std::vector<Bits128>& adj, int start, int cut_a, int cut_b) {
+// Call f(i) for every set bit i of b, in increasing order.
+template <class F>
+static inline void for_each_bit(const Bits128& b, F f) {
+    for (uint64_t w = b.lo; w; w &= w - 1) f(__builtin_ctzll(w));
+    for (uint64_t w = b.hi; w; w &= w - 1) f(64 + __builtin_ctzll(w));
+}
+
+// Atoms reachable from `start` without crossing the edge (cut_a, cut_b).
+static Bits128 flood(const Bits128* adj, int start, int cut_a, int cut_b) {
     Bits128 seen, frontier;
     seen.set(start);
     frontier.set(start);
-    const int n = (int)adj.size();
     while (frontier.lo | frontier.hi) {
         Bits128 next;
-        for (int i = 0; i < n; ++i) {
-            if (!frontier.test(i)) continue;
+        for_each_bit(frontier, [&](int i) {
             Bits128 a = adj[i];
             if (i == cut_a) a.clear(cut_b);
             if (i == cut_b) a.clear(cut_a);
             next |= a;
-        }
+        });
         Bits128 fresh;
         fresh.lo = next.lo & ~seen.lo;
         fresh.hi = next.hi & ~seen.hi;
@@ -67,7 +73,7 @@ int pack_ligand(int n, const int32_t* bond_ij, int nb, const int32_t* rot_bond, 
             return EXS_EINVAL;
         }
     }
-    std::vector<Bits128> adj(n);
+    Bits128 adj[EXS_MAX_ATOMS];
     for (int e = 0; e < nb; ++e) {
         int p = bond_ij[2 * e], q = bond_ij[2 * e + 1];
         if (p < 0 || p >= n || q < 0 || q >= n || p == q) {
@@ -81,15 +87,11 @@ int pack_ligand(int n, const int32_t* bond_ij, int nb, const int32_t* rot_bond, 
     out->n = n;
     out->nrot = nrot;
     // bond distance <= 1, then <= 2, then <= 3
-    std::vector<Bits128> d1(n), d2(n);
+    Bits128 d1[EXS_MAX_ATOMS], d2[EXS_MAX_ATOMS];
     for (int i = 0; i < n; ++i) { d1[i] = adj[i]; d1[i].set(i); }
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
-            if (d1[i].test(j)) d2[i] |= d1[j];
+    for (int i = 0; i < n; ++i) for_each_bit(d1[i], [&](int j) { d2[i] |= d1[j]; });
     out->excl.assign(n, Bits128());
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
-            if (d2[i].test(j)) out->excl[i] |= d1[j];
+    for (int i = 0; i < n; ++i) for_each_bit(d2[i], [&](int j) { out->excl[i] |= d1[j]; });
     out->rot_u.resize(nrot);
     out->rot_v.resize(nrot);
     out->moving.assign(nrot, Bits128());

@@ -328,6 +328,9 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
         return rt::fail(EXS_ENOMEM, "request of %d ligands / %d atoms exceeds the server arena", L, r->A);
     r->info.resize(L); r->ref.resize(r->A); r->ref64.resize((size_t)r->A * 3); r->excl.resize(r->A);
     r->ruv.resize(r->R); r->rmask.resize(r->R); r->cost.resize(L);
+    PackedLigand pk;            // reused across the request's ligands (keeps its capacity)
+    std::string err;
+    std::vector<int16_t> m;
     for (int l = 0; l < L; ++l) {
         if (in.atom_offset[l + 1] < in.atom_offset[l] || in.bond_offset[l + 1] < in.bond_offset[l] ||
             in.rot_offset[l + 1] < in.rot_offset[l])
@@ -338,8 +341,6 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
         int a0 = in.atom_offset[l], n = in.atom_offset[l + 1] - a0;
         int b0 = in.bond_offset[l], nb = in.bond_offset[l + 1] - b0;
         int r0 = in.rot_offset[l], nr = in.rot_offset[l + 1] - r0;
-        PackedLigand pk;
-        std::string err;
         int rc = pack_ligand(n, in.bond_ij + 2 * (size_t)b0, nb, in.rot_bond + r0, nr, in.type + a0,
                              channels_[ps->second], in.x + a0, in.y + a0, in.z + a0, &pk, &err);
         if (rc) return rt::fail(rc, "ligand %d: %s", l, err.c_str());
@@ -347,7 +348,7 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
         memset(&inf, 0, sizeof inf);
         inf.atom_base = a0; inf.rot_base = r0; inf.n = (int16_t)n; inf.nrot = (int16_t)nr;
         inf.pocket = (int16_t)ps->second;
-        std::vector<int16_t> m(nr);
+        m.assign(nr, 0);
         for (int i = 0; i < n; ++i) {
             double dx = (double)in.x[a0 + i] - pk.centroid[0], dy = (double)in.y[a0 + i] - pk.centroid[1],
                    dz = (double)in.z[a0 + i] - pk.centroid[2];
