@@ -164,6 +164,18 @@ hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int n
 // (8, 16 or 32) independent lookups per round.
 hipError_t launch_gather_probe(const GridDesc* gd, int storage, int nb, int64_t blocks, int per_lane,
                                float half, float walk, uint32_t seed, float* out, hipStream_t st);
+// Serving: the results of one iteration's ligands, gathered into contiguous staging (one
+// record per ligand, then coordinates and torsion bytes at host-computed offsets).
+struct ResultRec {
+    float score;
+    int32_t k;
+    int32_t tau;
+    int32_t pad;
+    double score64;
+};
+hipError_t launch_gather_results(const int32_t* lig, const int32_t* atom_dst, const int32_t* rot_dst,
+                                 int n, const DockArgs& a, ResultRec* rec, float* coords,
+                                 uint8_t* theta, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 hipError_t upload_trig_tables();
 const void* dock_kernel_fn(int storage, int S, int ppl);

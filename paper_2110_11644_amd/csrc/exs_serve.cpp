@@ -122,12 +122,20 @@ struct Request {
 struct Iteration {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    // index upload (pinned host, device): processing order [n], queue bounds [kXcds + 1],
+    // then per work-list ligand j: arena ligand [n], staging atom offset [n], staging bond offset [n]
     int32_t* d_order = nullptr;
-    int32_t* h_order = nullptr;   // pinned
+    int32_t* h_order = nullptr;
     int* d_counter = nullptr;
     float* scratch = nullptr;
+    // result staging: device, and its pinned host copy (records | coordinates | torsion bytes)
+    ResultRec* d_rec = nullptr;
+    float* d_coords = nullptr;
+    uint8_t* d_theta = nullptr;
+    unsigned char* h_res = nullptr;
     bool running = false;
-    std::vector<std::pair<Request*, int>> work;   // (request, ligands scheduled)
+    struct Work { Request* r; int start, count; };   // ligands start .. start+count-1 of r
+    std::vector<Work> work;
     Clock::time_point t_launch;
 };
 
@@ -153,6 +161,7 @@ class Server {
     exs_search_params prm_{};
     int K_ = 0, ppl_ = 1, lpw_ = 1, wpl_ = 1, threads_ = 64, top_k_ = 0, storage_ = 0;
     int resident_ = 1, max_iter_ = 0, n_iters_ = 2;
+    size_t res_rec_bytes_ = 0, res_coord_bytes_ = 0, res_theta_bytes_ = 0;   // staging regions
     size_t lds_ = 0;
     std::vector<int32_t> pocket_ids_;
     std::unordered_map<int32_t, int> pocket_slot_;
@@ -160,7 +169,7 @@ class Server {
     DockArgs base_{};
     std::vector<void*> dev_bufs_;
     RangeAlloc lig_alloc_, atom_alloc_, rot_alloc_;
-    hipStream_t up_stream_ = nullptr, copy_stream_ = nullptr;
+    hipStream_t up_stream_ = nullptr;
     hipEvent_t up_event_ = nullptr;
     bool up_pending_ = false;
     Iteration it_[2];
@@ -235,7 +244,11 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     max_iter_ = cfg.max_iter_ligands > 0 ? cfg.max_iter_ligands : 2 * resident_ * lpw_;
     // budget: scratch for the iterations first, the rest is the request arena
     const int64_t slot_floats = (int64_t)lpw_ * EXS_MAX_ATOMS * 3 * (wpl_ * kWave * ppl_);
-    const int64_t scratch_bytes = (int64_t)n_iters_ * resident_ * slot_floats * 4;
+    res_rec_bytes_ = sizeof(ResultRec) * (size_t)max_iter_;
+    res_coord_bytes_ = sizeof(float) * 3 * (size_t)EXS_MAX_ATOMS * max_iter_;
+    res_theta_bytes_ = (size_t)EXS_MAX_ROT * max_iter_;
+    const int64_t scratch_bytes = (int64_t)n_iters_ * resident_ * slot_floats * 4 +
+                                  (int64_t)n_iters_ * (res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_);
     const int64_t per_lig = 32 + 12LL * K_ + 40 + 28LL * top_k_ + 4;   // info, per-orientation, best, top-k, order
     const int64_t per_atom = 16 + 24 + 16 + 12;
     const int64_t per_rot = 4 + 16 + K_ + 1 + top_k_;
@@ -291,17 +304,21 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     a.slot_floats = slot_floats;
     a.persistent = 1;
     SRV_TRY(hipStreamCreateWithFlags(&up_stream_, hipStreamNonBlocking));
-    SRV_TRY(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking));
     SRV_TRY(hipEventCreateWithFlags(&up_event_, hipEventDisableTiming));
     for (int i = 0; i < n_iters_; ++i) {
         Iteration& it = it_[i];
         SRV_TRY(hipStreamCreateWithFlags(&it.stream, hipStreamNonBlocking));
         SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
-        if ((rc = dev_alloc(dev_bufs_, &it.d_order, max_iter_ + kXcds + 1)) ||
+        if ((rc = dev_alloc(dev_bufs_, &it.d_order, 4 * (size_t)max_iter_ + kXcds + 1)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_counter, kXcds)) ||
-            (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)))
+            (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_rec, (size_t)max_iter_)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_coords, (size_t)3 * EXS_MAX_ATOMS * max_iter_)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_theta, (size_t)EXS_MAX_ROT * max_iter_)))
             return rc;
-        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (max_iter_ + kXcds + 1),
+        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (4 * (size_t)max_iter_ + kXcds + 1),
+                              hipHostMallocDefault));
+        SRV_TRY(hipHostMalloc((void**)&it.h_res, res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_,
                               hipHostMallocDefault));
     }
     pocket_ids_.assign(pockets, pockets + n_pockets);
@@ -328,6 +345,7 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
         return rt::fail(EXS_ENOMEM, "request of %d ligands / %d atoms exceeds the server arena", L, r->A);
     r->info.resize(L); r->ref.resize(r->A); r->ref64.resize((size_t)r->A * 3); r->excl.resize(r->A);
     r->ruv.resize(r->R); r->rmask.resize(r->R); r->cost.resize(L);
+    r->best_score.resize(L); r->desc.resize(L); r->coords.resize((size_t)r->A * 3);
     PackedLigand pk;            // reused across the request's ligands (keeps its capacity)
     std::string err;
     std::vector<int16_t> m;
@@ -417,43 +435,73 @@ bool Server::admit_locked() {
 }
 
 bool Server::launch(Iteration& it) {
-    // oldest requests first, up to max_iter_ ligands
+    // oldest requests first, up to max_iter_ ligands; j = position in this work list
     std::vector<double> cost;
     std::vector<int> pocket;
-    std::vector<int32_t> lig;
+    std::vector<int32_t> lig, nat, nrt;
     it.work.clear();
     for (Request* r : inflight_) {
         if ((int)lig.size() >= max_iter_) break;
         int take = std::min(r->L - r->scheduled, max_iter_ - (int)lig.size());
         if (take <= 0) continue;
         for (int i = 0; i < take; ++i) {
+            const LigInfo& inf = r->info[r->scheduled + i];
             cost.push_back(r->cost[r->scheduled + i]);
-            pocket.push_back(r->info[r->scheduled + i].pocket);
+            pocket.push_back(inf.pocket);
             lig.push_back(r->lig0 + r->scheduled + i);
+            nat.push_back(inf.n);
+            nrt.push_back(inf.nrot);
         }
+        it.work.push_back({r, r->scheduled, take});
         r->scheduled += take;
-        it.work.emplace_back(r, take);
     }
     if (lig.empty()) return false;
-    // per-XCD queues (pocket-major, equal cost, longest first), bounds after the order
+    // per-XCD queues (pocket-major, equal cost, longest first), then the gather's indices
     const int n = (int)lig.size();
+    int32_t* h_ord = it.h_order;
+    int32_t* h_bounds = h_ord + n;
+    int32_t* h_lig = h_bounds + kXcds + 1;
+    int32_t* h_adst = h_lig + n;
+    int32_t* h_rdst = h_adst + n;
     std::vector<int32_t> ord(n);
-    xcd_queues(n, pocket.data(), cost.data(), kXcds, ord.data(), it.h_order + n);
-    for (int i = 0; i < n; ++i) it.h_order[i] = lig[ord[i]];
+    xcd_queues(n, pocket.data(), cost.data(), kXcds, ord.data(), h_bounds);
+    int atoms = 0, rots = 0;
+    for (int j = 0; j < n; ++j) {
+        h_ord[j] = lig[ord[j]];
+        h_lig[j] = lig[j];
+        h_adst[j] = atoms;
+        h_rdst[j] = rots;
+        atoms += nat[j];
+        rots += nrt[j];
+    }
+    const int32_t* d_bounds = it.d_order + n;
+    const int32_t* d_lig = d_bounds + kXcds + 1;
     if (up_pending_) (void)hipStreamWaitEvent(it.stream, up_event_, 0);
     DockArgs a = base_;
     a.order = it.d_order;
     a.n_order = n;
     a.n_tiles = (a.n_order + lpw_ - 1) / lpw_;
     a.tile_counter = it.d_counter;
-    a.queue_bounds = it.d_order + n;
+    a.queue_bounds = d_bounds;
     a.n_queues = kXcds;
     a.scratch = it.scratch;
-    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (n + kXcds + 1),
+    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (4 * (size_t)n + kXcds + 1),
                                   hipMemcpyHostToDevice, it.stream);
     if (e == hipSuccess) e = launch_zero_ints(it.d_counter, kXcds, it.stream);
     if (e == hipSuccess)
         e = launch_dock(a, storage_, ppl_, std::min(resident_, a.n_tiles), threads_, lds_, it.stream);
+    // results of this work list into staging, then one copy per staging region to pinned memory
+    if (e == hipSuccess)
+        e = launch_gather_results(d_lig, d_lig + n, d_lig + 2 * n, n, a, it.d_rec, it.d_coords,
+                                  it.d_theta, it.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(it.h_res, it.d_rec, sizeof(ResultRec) * n, hipMemcpyDeviceToHost, it.stream);
+    if (e == hipSuccess && atoms > 0)
+        e = hipMemcpyAsync(it.h_res + res_rec_bytes_, it.d_coords, sizeof(float) * 3 * atoms,
+                           hipMemcpyDeviceToHost, it.stream);
+    if (e == hipSuccess && rots > 0)
+        e = hipMemcpyAsync(it.h_res + res_rec_bytes_ + res_coord_bytes_, it.d_theta, rots,
+                           hipMemcpyDeviceToHost, it.stream);
     if (e == hipSuccess) e = hipEventRecord(it.done, it.stream);
     if (e != hipSuccess) {
         thread_error_ = hipGetErrorString(e);
@@ -468,41 +516,35 @@ bool Server::launch(Iteration& it) {
 void Server::complete(Iteration& it) {
     it.running = false;
     busy_ms_ += std::chrono::duration<double, std::milli>(Clock::now() - it.t_launch).count();
-    for (auto& w : it.work) {
-        Request* r = w.first;
-        r->remaining -= w.second;
-        ligands_ += w.second;
-        if (r->remaining > 0) continue;
-        // copy the results out, then free the arena ranges
-        const DockArgs& a = base_;
-        std::vector<int32_t> bk(r->L), bt(r->L);
-        std::vector<uint8_t> th(r->R);
-        std::vector<double> b64(r->L, NAN);
-        r->best_score.resize(r->L);
-        r->coords.resize((size_t)r->A * 3);
-        (void)hipMemcpyAsync(r->best_score.data(), a.best_score + r->lig0, sizeof(float) * r->L, hipMemcpyDeviceToHost, copy_stream_);
-        (void)hipMemcpyAsync(bk.data(), a.best_k + r->lig0, sizeof(int32_t) * r->L, hipMemcpyDeviceToHost, copy_stream_);
-        (void)hipMemcpyAsync(bt.data(), a.best_tau + r->lig0, sizeof(int32_t) * r->L, hipMemcpyDeviceToHost, copy_stream_);
-        if (r->R) (void)hipMemcpyAsync(th.data(), a.best_theta + r->rot0, r->R, hipMemcpyDeviceToHost, copy_stream_);
-        if (top_k_ > 0) (void)hipMemcpyAsync(b64.data(), a.best_score64 + r->lig0, sizeof(double) * r->L, hipMemcpyDeviceToHost, copy_stream_);
-        if (r->A) (void)hipMemcpyAsync(r->coords.data(), a.best_coords + (size_t)r->atom0 * 3, sizeof(float) * 3 * r->A, hipMemcpyDeviceToHost, copy_stream_);
-        (void)hipStreamSynchronize(copy_stream_);
-        r->desc.resize(r->L);
-        for (int l = 0; l < r->L; ++l) {
+    const ResultRec* rec = reinterpret_cast<const ResultRec*>(it.h_res);
+    const float* co = reinterpret_cast<const float*>(it.h_res + res_rec_bytes_);
+    const uint8_t* th = it.h_res + res_rec_bytes_ + res_coord_bytes_;
+    int j = 0;
+    size_t atom = 0, rot = 0;
+    for (const Iteration::Work& w : it.work) {
+        Request* r = w.r;
+        for (int l = w.start; l < w.start + w.count; ++l, ++j) {
+            const LigInfo& inf = r->info[l];
+            const ResultRec& rr = rec[j];
             exs_pose_desc& d = r->desc[l];
             memset(&d, 0, sizeof d);
-            d.score = r->best_score[l];
-            d.score_fp64 = b64[l];
-            d.orient = bk[l];
-            d.tau[0] = (int8_t)(bt[l] & 0xff);
-            d.tau[1] = (int8_t)((bt[l] >> 8) & 0xff);
-            d.tau[2] = (int8_t)((bt[l] >> 16) & 0xff);
-            const LigInfo& inf = r->info[l];
+            d.score = rr.score;
+            d.score_fp64 = top_k_ > 0 ? rr.score64 : NAN;
+            d.orient = rr.k;
+            d.tau[0] = (int8_t)(rr.tau & 0xff);
+            d.tau[1] = (int8_t)((rr.tau >> 8) & 0xff);
+            d.tau[2] = (int8_t)((rr.tau >> 16) & 0xff);
             d.n_rot = (uint8_t)inf.nrot;
-            for (int b = 0; b < inf.nrot; ++b) d.theta[b] = th[inf.rot_base - r->rot0 + b];
+            memcpy(d.theta, th + rot, inf.nrot);
+            r->best_score[l] = top_k_ > 0 ? (float)rr.score64 : rr.score;
+            memcpy(&r->coords[(size_t)(inf.atom_base - r->atom0) * 3], co + atom * 3,
+                   sizeof(float) * 3 * inf.n);
+            atom += inf.n;
+            rot += inf.nrot;
         }
-        if (top_k_ > 0)
-            for (int l = 0; l < r->L; ++l) r->best_score[l] = (float)b64[l];
+        r->remaining -= w.count;
+        ligands_ += w.count;
+        if (r->remaining > 0) continue;
         lig_alloc_.release(r->lig0, r->L);
         atom_alloc_.release(r->atom0, r->A);
         rot_alloc_.release(r->rot0, r->R);
@@ -602,12 +644,12 @@ void Server::shutdown() {
         if (it.stream) { (void)hipStreamSynchronize(it.stream); (void)hipStreamDestroy(it.stream); }
         if (it.done) (void)hipEventDestroy(it.done);
         if (it.h_order) (void)hipHostFree(it.h_order);
+        if (it.h_res) (void)hipHostFree(it.h_res);
         it = Iteration();
     }
     if (up_stream_) { (void)hipStreamSynchronize(up_stream_); (void)hipStreamDestroy(up_stream_); }
-    if (copy_stream_) (void)hipStreamDestroy(copy_stream_);
     if (up_event_) (void)hipEventDestroy(up_event_);
-    up_stream_ = copy_stream_ = nullptr;
+    up_stream_ = nullptr;
     up_event_ = nullptr;
     for (void* p : dev_bufs_) (void)hipFree(p);
     dev_bufs_.clear();
