@@ -65,15 +65,23 @@ def algorithmic_counts(binding, batch, search, channels):
     return L, Q, R
 
 
+def kernel_source_sha256():
+    """SHA-256 of the dock kernel's sources (the search and its texel gathers)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("dock_kernels.inc", "texel_gather.inc"):
+        with open(os.path.join(ROOT, "paper_2110_11644_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(n_ligands):
     """HBM bytes of one dock launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
     or None if the dock kernel's source changed since those counters were taken."""
-    import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "dock_kernel_scale_traffic.json")) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_2110_11644_amd", "csrc", "dock_kernels.inc"), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
+        h = kernel_source_sha256()
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != h:
