@@ -82,6 +82,10 @@ def lib():
         L.orc_dock_batch.argtypes = [C.POINTER(_Grid), C.c_int, C.POINTER(_Params), C.c_int,
                                      _ip, _fp, _fp, _fp, _up, _ip, _ip, _ip, _ip, _ip,
                                      _ip, _dp, _dp, _ip, _ip, _ip, C.c_int]
+        L.orc_rmsd.restype = C.c_double
+        L.orc_rmsd.argtypes = [C.c_int, _dp, _dp]
+        L.orc_rank_poses.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double,
+                                     C.c_double, _ip, _ip, _ip, _ip]
         _lib = L
     return _lib
 
@@ -242,6 +246,34 @@ def dock_ligand(grid: Grid, params: Params, lig, coords: bool = False, trace_cap
     out["best_score"] = bs.value
     out["near_tie"] = out["near_tie"].astype(bool)
     return out
+
+
+def rmsd(a: np.ndarray, b: np.ndarray) -> float:
+    """RMSD of two poses [n,3] of one ligand, same frame (Sec. 3.1, third step)."""
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    return float(lib().orc_rmsd(a.shape[0], _ptr(a, _dp), _ptr(b, _dp)))
+
+
+def rank_poses(poses: np.ndarray, scores: np.ndarray, thr: float = 3.0, delta: float = 1e-4,
+               tol: float = 1e-4) -> dict:
+    """Sec. 3.1, third step: cluster the K poses [K,n,3] with the RMSD threshold (greedy
+    leaders in score order) and list the leaders by score, then the rest by score.  Returns
+    order [K], leader [K] (bool), n_leaders, and the ambiguity counts (RMSD within delta of
+    thr; adjacent scores closer than tol * max(|s|, 1))."""
+    poses = np.ascontiguousarray(poses, np.float64)
+    scores = np.ascontiguousarray(scores, np.float64)
+    K, n = poses.shape[0], poses.shape[1]
+    order = np.zeros(K, np.int32)
+    leader = np.zeros(K, np.int32)
+    ar, asc = C.c_int(), C.c_int()
+    nl = lib().orc_rank_poses(K, n, _ptr(poses, _dp), _ptr(scores, _dp), float(thr), float(delta),
+                              float(tol), _ptr(order, _ip), _ptr(leader, _ip), C.byref(ar),
+                              C.byref(asc))
+    if nl < 0:
+        _check(nl)
+    return dict(order=order, leader=leader.astype(bool), n_leaders=int(nl),
+                amb_rmsd=int(ar.value), amb_score=int(asc.value))
 
 
 def dock_batch(grids: Sequence[Grid], params: Params, batch, threads: Optional[int] = None,

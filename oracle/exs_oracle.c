@@ -589,3 +589,88 @@ int orc_dock_batch(const orc_grid *grids, int n_grids, const orc_params *prm, in
     }
     return err;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Ranking of the final poses (third step of the method)                    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Sec. 3.1, third step: the generated poses of a ligand are clustered with an
+ * RMSD threshold (two poses are similar when their RMSD is below it), then
+ * listed with the best-scoring pose of every cluster first and all the other
+ * poses after them, each group by the (geometric) score.  The paper names
+ * neither the RMSD nor the clustering procedure; the readings are:
+ *   RMSD(a, b) = sqrt(mean_i |a_i - b_i|^2) over all atoms, same frame (no
+ *            superposition: the poses share the pocket's frame);
+ *   clusters  greedy leaders: poses taken by score (lower first, ties to the
+ *            lower orientation index); a pose starts a new cluster (is a
+ *            leader) unless its RMSD to some earlier leader is below thr.
+ * A leader is then the best-scoring pose of its cluster.
+ */
+double orc_rmsd(int n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < 3 * n; ++i) {
+        double d = a[i] - b[i];
+        s += d * d;
+    }
+    return sqrt(s / (double)n);
+}
+
+/* poses [K][n][3], scores [K].  Out: order [K] (pose indices, leaders by score
+ * then the others by score), leader [K] (1 for a leader).  Returns the number of
+ * leaders (or < 0 on bad arguments).  Oracle bookkeeping: *amb_rmsd counts the
+ * leader tests whose RMSD lies within delta of thr; *amb_score counts pairs of
+ * poses adjacent in score order whose scores differ by less than
+ * tol * max(|s|, 1) (either may be taken first in another precision). */
+int orc_rank_poses(int K, int n, const double *poses, const double *scores, double thr,
+                   double delta, double tol, int *order, int *leader, int *amb_rmsd,
+                   int *amb_score)
+{
+    if (K < 1 || n < 1 || !poses || !scores || !order || !leader) return ORC_EINVAL;
+    int *by_score = (int *)malloc(sizeof(int) * (size_t)K);
+    int *leaders = (int *)malloc(sizeof(int) * (size_t)K);
+    if (!by_score || !leaders) { free(by_score); free(leaders); return ORC_ENOMEM; }
+    /* 1. poses by score: insertion sort on (score, index), NaN last */
+    for (int k = 0; k < K; ++k) {
+        int j = k;
+        double s = scores[k];
+        while (j > 0) {
+            int p = by_score[j - 1];
+            double sp = scores[p];
+            int before = isnan(s) ? 0 : (isnan(sp) ? 1 : (s < sp));   /* k before p? */
+            if (!before) break;
+            by_score[j] = p;
+            --j;
+        }
+        by_score[j] = k;
+    }
+    int ns = 0;
+    for (int j = 0; j + 1 < K; ++j) {
+        double a = scores[by_score[j]], b = scores[by_score[j + 1]];
+        double m = fabs(a) > 1.0 ? fabs(a) : 1.0;
+        if (fabs(a - b) < tol * m) ++ns;
+    }
+    /* 2. greedy leaders */
+    int nl = 0, nr = 0;
+    for (int j = 0; j < K; ++j) {
+        int p = by_score[j];
+        int similar = 0;
+        for (int q = 0; q < nl; ++q) {
+            double r = orc_rmsd(n, poses + (size_t)p * n * 3, poses + (size_t)leaders[q] * n * 3);
+            if (fabs(r - thr) < delta) ++nr;
+            if (r < thr) similar = 1;
+        }
+        leader[p] = !similar;
+        if (!similar) leaders[nl++] = p;
+    }
+    /* 3. leaders by score, then the others by score */
+    int o = 0;
+    for (int j = 0; j < K; ++j) if (leader[by_score[j]]) order[o++] = by_score[j];
+    for (int j = 0; j < K; ++j) if (!leader[by_score[j]]) order[o++] = by_score[j];
+    if (amb_rmsd) *amb_rmsd = nr;
+    if (amb_score) *amb_score = ns;
+    free(by_score);
+    free(leaders);
+    return nl;
+}

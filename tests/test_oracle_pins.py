@@ -456,3 +456,98 @@ def test_oracle_regression_fixture(oracle_lib):
         assert r["best_k"] == entry["best_k"]
         assert np.allclose(r["score"], entry["score"], rtol=1e-12, atol=1e-12)
         assert r["theta"].tolist() == entry["theta"]
+
+
+# ------------------------------------------------------------------------------------------------
+# Ranking of the final poses: RMSD clustering, leaders first (Sec. 3.1, third step)
+
+
+def test_rmsd_closed_forms(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(7, 3))
+    assert O.rmsd(X, X) == 0.0
+    t = np.array([1.0, 2.0, 2.0])
+    assert abs(O.rmsd(X, X + t) - 3.0) < 1e-12                  # a translation moves every atom by |t|
+    R = np.diag([-1.0, -1.0, 1.0])                              # half turn about z
+    P = np.array([[2.0, 0.0, 5.0], [0.0, 1.0, -1.0]])
+    # distances 2*2 and 2*1 -> sqrt((16 + 4) / 2)
+    assert abs(O.rmsd(P, P @ R.T) - np.sqrt(10.0)) < 1e-12
+    Y = rng.normal(size=(7, 3))
+    assert O.rmsd(X, Y) == O.rmsd(Y, X)
+
+
+def test_rank_poses_on_a_line(oracle_lib):
+    """Rigid copies of a 2-atom pose 1 A apart along x, better first: leaders every 3 A, a pose
+    exactly 3 A from a leader starts its own cluster (similar means below the threshold)."""
+    O = oracle_lib
+    K = 8
+    poses = np.zeros((K, 2, 3))
+    poses[:, 1, 1] = 1.5
+    poses[:, :, 0] += np.arange(K)[:, None]
+    r = O.rank_poses(poses, np.arange(K, dtype=float), 3.0)
+    assert r["leader"].tolist() == [True, False, False, True, False, False, True, False]
+    assert r["order"].tolist() == [0, 3, 6, 1, 2, 4, 5, 7]
+    assert r["n_leaders"] == 3 and r["amb_rmsd"] == 2
+    r = O.rank_poses(poses, np.arange(K, dtype=float), 3.0 + 1e-9)
+    assert r["leader"].tolist() == [True, False, False, False, True, False, False, False]
+    # the scores, not the indices, decide who leads: reverse them
+    r = O.rank_poses(poses, -np.arange(K, dtype=float), 3.0)
+    assert r["order"][0] == K - 1 and r["leader"][K - 1] and r["leader"][K - 4]
+
+
+def _check_greedy_leaders(O, poses, scores, thr, r):
+    """The output of the ranking is fixed by these properties (the first pose where two
+    outputs differ would contradict one of them): a permutation; leaders listed by score
+    and then the others by score; every leader at RMSD >= thr from every better leader;
+    every other pose below thr from some better leader."""
+    K = len(scores)
+    order = r["order"]
+    assert sorted(order.tolist()) == list(range(K))
+    by = sorted(range(K), key=lambda k: (scores[k], k))
+    pos = {k: i for i, k in enumerate(by)}
+    lead = [k for k in by if r["leader"][k]]
+    rest = [k for k in by if not r["leader"][k]]
+    assert order.tolist() == lead + rest
+    for k in by:
+        better = [q for q in lead if pos[q] < pos[k]]
+        d = [O.rmsd(poses[k], poses[q]) for q in better]
+        if r["leader"][k]:
+            assert all(x >= thr for x in d)
+        else:
+            assert any(x < thr for x in d)
+
+
+def test_rank_poses_properties_on_random_poses(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        K, n = int(rng.integers(5, 60)), int(rng.integers(1, 12))
+        base = rng.normal(size=(n, 3)) * 2.0
+        poses = base[None] + rng.normal(size=(K, 1, 3)) * rng.uniform(1.0, 4.0) \
+            + rng.normal(size=(K, n, 3)) * 0.5
+        scores = np.round(rng.normal(size=K), 1)                 # ties on purpose
+        thr = float(rng.uniform(0.5, 5.0))
+        r = O.rank_poses(poses, scores, thr)
+        _check_greedy_leaders(O, poses, scores, thr, r)
+
+
+def test_rank_poses_special_cases(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(5)
+    K, n = 40, 6
+    poses = rng.normal(size=(K, n, 3)) * 3.0
+    scores = rng.normal(size=K)
+    scores[7] = scores[3]                                        # a tie: index 3 goes first
+    by = np.lexsort((np.arange(K), scores))
+    r = O.rank_poses(poses, scores, 0.0)                         # nothing is similar
+    assert r["n_leaders"] == K and r["order"].tolist() == by.tolist()
+    r = O.rank_poses(poses, scores, np.inf)                      # everything is similar
+    assert r["n_leaders"] == 1 and r["order"].tolist() == by.tolist()
+    same = np.repeat(poses[:1], K, axis=0)
+    r = O.rank_poses(same, scores, 1e-9)                         # identical poses: one cluster
+    assert r["n_leaders"] == 1 and r["order"].tolist() == by.tolist()
+    s2 = scores.copy()
+    s2[[0, 9]] = np.nan                                          # NaN scores rank last
+    r = O.rank_poses(poses, s2, 0.0)
+    assert r["order"][-2:].tolist() == [0, 9]
