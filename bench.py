@@ -496,6 +496,9 @@ def main():
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "small", "batched", "precision", "serving"])
     ap.add_argument("--tune", action="store_true", help="autotune the tile (batched)")
+    ap.add_argument("--rank-keep", type=int, default=0,
+                    help="scale/small: rank each ligand's final poses and keep this many (0 = off)")
+    ap.add_argument("--cluster-rmsd", type=float, default=3.0, help="ranking: RMSD threshold (A)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: timed requests")
     ap.add_argument("--sweep", default="0.5,0.9", help="serving: other offered loads to serve")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
@@ -553,7 +556,8 @@ def main():
     flags = B.EXS_FLAG_PERSISTENT if args.persistent else 0
     prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                           s.clash_cutoff, s.clash_penalty, top_k=0, poses_per_lane=args.ppl,
-                          ligands_per_wg=args.lpw, flags=flags)
+                          ligands_per_wg=args.lpw, flags=flags, cluster_rmsd_A=args.cluster_rmsd,
+                          rank_keep=args.rank_keep)
     L, A = batch.n_ligands, int(batch.atom_offset[-1])
 
     def step():
@@ -614,6 +618,7 @@ def main():
                             "one persistent launch" if args.persistent else "one launch per pocket"),
             "ligands": L, "atoms": A, "parallelism": "single GPU",
             "poses_per_lane": args.ppl, "ligands_per_wg": args.lpw,
+            "rank_keep": args.rank_keep, "cluster_rmsd_A": args.cluster_rmsd if args.rank_keep else None,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

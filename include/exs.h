@@ -85,6 +85,17 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
                          int values_on_device, void* stream, int32_t* pocket_id_out);
 
 /*
+ * Ranked poses of a job run with rank_keep > 0 (Sec. 3.1, third step: cluster
+ * leaders first, then the other poses, each by score).
+ *   n_clusters  [L] clusters (leaders) per ligand, or NULL
+ *   ranked      [L * rank_keep] orientation indices per ligand in ranked order,
+ *               or NULL
+ * wait = 0 returns EXS_ENOTREADY while the job runs.  Errors: EXS_ENOENT,
+ * EXS_EINVAL (the job did not rank), EXS_EDEVICE.
+ */
+int exs_get_ranked_poses(int64_t job, int wait, int32_t* n_clusters, int32_t* ranked);
+
+/*
  * Gather probe: the docking kernels' texel lookup (same per-cell blocks, loads and FP32
  * trilinear arithmetic) alone, to measure the lookup rate the search is held against
  * (Sec. 3.1: the score of a pose is a lookup per atom in the pocket's grids).
@@ -180,6 +191,15 @@ int exs_pack_topology(int n, const float* x, const float* y, const float* z, con
  *   poses_per_lane 0 = auto, or 1, 2, 4 (orientations searched by one lane)
  *   ligands_per_wg 0 = auto, or 1, 2, 4, 8 (ligands per workgroup)
  *   flags          EXS_FLAG_* bits
+ *   cluster_rmsd_A, rank_keep   ranking of each ligand's K final poses (Sec. 3.1,
+ *                  third step), when rank_keep > 0: poses by score (lower
+ *                  first, ties to the lower orientation), greedy clusters (a pose
+ *                  leads a new cluster unless its RMSD, over all atoms in the
+ *                  pocket frame, to an earlier leader is below cluster_rmsd_A),
+ *                  then the leaders by score followed by the other poses by
+ *                  score; the first rank_keep (<= n_orient) orientations of that
+ *                  list are kept (exs_get_ranked_poses).  0 = no ranking.  Not
+ *                  supported by the serving engine.
  */
 typedef struct {
     int32_t n_orient;
@@ -193,6 +213,8 @@ typedef struct {
     int32_t poses_per_lane;
     int32_t ligands_per_wg;
     int32_t flags;
+    float cluster_rmsd_A;
+    int32_t rank_keep;
 } exs_search_params;
 
 /*

@@ -26,7 +26,8 @@ STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
 # exported symbols (kept in step with include/exs.h)
 SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
            "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
-           "exs_get_orientation_results", "exs_job_elapsed_ms", "exs_release_job", "exs_gather_probe",
+           "exs_get_orientation_results", "exs_get_ranked_poses", "exs_job_elapsed_ms",
+           "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
            "exs_server_destroy")
 
@@ -49,7 +50,8 @@ class exs_search_params(C.Structure):
                 ("n_offsets", C.c_int32), ("offset_step_A", C.c_float),
                 ("clash_cutoff_A", C.c_float), ("clash_penalty", C.c_float),
                 ("top_k", C.c_int32), ("poses_per_lane", C.c_int32),
-                ("ligands_per_wg", C.c_int32), ("flags", C.c_int32)]
+                ("ligands_per_wg", C.c_int32), ("flags", C.c_int32),
+                ("cluster_rmsd_A", C.c_float), ("rank_keep", C.c_int32)]
 
 
 class exs_server_config(C.Structure):
@@ -95,6 +97,7 @@ def lib():
         L.exs_get_orientation_results.argtypes = [i64, vp, vp]
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
+        L.exs_get_ranked_poses.argtypes = [i64, C.c_int, vp, vp]
         L.exs_gather_probe.argtypes = [i32, i64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_uint32, vp,
                                        C.POINTER(C.c_float), C.POINTER(C.c_double)]
         L.exs_server_create.argtypes = [vp, C.c_int, C.POINTER(exs_search_params),
@@ -212,10 +215,11 @@ def exs_pack_topology(lig, channels: int) -> dict:
 def search_params(n_orient: int, torsion_steps: int, passes: int, n_offsets: int,
                   offset_step_A: float = 0.5, clash_cutoff_A: float = 2.0,
                   clash_penalty: float = 1.0, top_k: int = 0, poses_per_lane: int = 0,
-                  ligands_per_wg: int = 0, flags: int = 0) -> exs_search_params:
+                  ligands_per_wg: int = 0, flags: int = 0, cluster_rmsd_A: float = 3.0,
+                  rank_keep: int = 0) -> exs_search_params:
     return exs_search_params(n_orient, torsion_steps, passes, n_offsets, offset_step_A,
                              clash_cutoff_A, clash_penalty, top_k, poses_per_lane,
-                             ligands_per_wg, flags)
+                             ligands_per_wg, flags, cluster_rmsd_A, rank_keep)
 
 
 def exs_dock_batch(batch_id: int, params: exs_search_params, stream=None) -> int:
@@ -241,6 +245,14 @@ def exs_get_orientation_results(job: int, n_ligands: int, n_orient: int) -> dict
     desc = np.zeros(n_ligands * n_orient, POSE_DESC)
     _check(lib().exs_get_orientation_results(int(job), _p(sc), _p(desc)))
     return dict(score=sc.reshape(n_ligands, n_orient), desc=desc.reshape(n_ligands, n_orient))
+
+
+def exs_get_ranked_poses(job: int, n_ligands: int, rank_keep: int, wait: bool = True):
+    """(n_clusters [L], ranked [L, rank_keep]) of a job run with rank_keep > 0."""
+    nc = np.zeros(n_ligands, np.int32)
+    rk = np.zeros((n_ligands, rank_keep), np.int32)
+    _check(lib().exs_get_ranked_poses(int(job), 1 if wait else 0, _p(nc), _p(rk)))
+    return nc, rk
 
 
 def exs_job_elapsed_ms(job: int) -> float:

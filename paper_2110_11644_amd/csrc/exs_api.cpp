@@ -724,6 +724,10 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
             return fail(EXS_EINVAL, "offset step, clash cutoff and penalty must be finite, >= 0");
         if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return fail(EXS_EINVAL, "top_k %d outside [0, %d]", p.top_k, EXS_MAX_TOPK);
         if (p.n_offsets == 27 && p.passes > 127) return fail(EXS_EINVAL, "too many passes for offsets");
+        if (p.rank_keep < 0 || p.rank_keep > p.n_orient)
+            return fail(EXS_EINVAL, "rank_keep %d outside [0, n_orient]", p.rank_keep);
+        if (p.rank_keep > 0 && (!(p.cluster_rmsd_A >= 0.0f) || !isfinite(p.cluster_rmsd_A)))
+            return fail(EXS_EINVAL, "cluster_rmsd_A must be finite and >= 0");
         int ppl = p.poses_per_lane ? p.poses_per_lane : 1;
         if (ppl != 1 && ppl != 2) return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2", ppl);
         const int K = p.n_orient;
@@ -797,7 +801,8 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
             plan_key = {K, p.torsion_steps, p.passes, p.n_offsets, top_k, ppl, lpw, p.flags,
                         (int64_t)__builtin_bit_cast(uint32_t, p.offset_step_A),
                         (int64_t)__builtin_bit_cast(uint32_t, p.clash_cutoff_A),
-                        (int64_t)__builtin_bit_cast(uint32_t, p.clash_penalty)};
+                        (int64_t)__builtin_bit_cast(uint32_t, p.clash_penalty), p.rank_keep,
+                        (int64_t)__builtin_bit_cast(uint32_t, p.cluster_rmsd_A)};
             std::lock_guard<std::mutex> lk(b->order_mu);
             auto it = b->plans.find(plan_key);
             if (it != b->plans.end()) plan = it->second;
@@ -822,6 +827,8 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
             a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
             a.pen64 = (double)p.clash_penalty;
             a.top_k = top_k; a.lpw = lpw; a.wpl = wpl; a.kp = wpl * kWave * ppl;
+            a.rank_keep = p.rank_keep;
+            a.rank_thr2 = p.cluster_rmsd_A * p.cluster_rmsd_A;
             a.n_max = b->n_max;
             a.slot_floats = (int64_t)lpw * a.n_max * 3 * a.kp;
             std::shared_ptr<Plan> fresh;
@@ -843,6 +850,8 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 (rc = job_alloc(al, &a.topk_score64, (size_t)L * top_k)) ||
                 (rc = job_alloc(al, &a.topk_theta, (size_t)R * top_k)) ||
                 (rc = job_alloc(al, &a.topk_tau, (size_t)L * top_k)) ||
+                (rc = job_alloc(al, &a.n_clusters, (size_t)L)) ||
+                (rc = job_alloc(al, &a.ranked, (size_t)L * p.rank_keep)) ||
                 (rc = job_alloc(al, &a.tile_counter, (size_t)kXcds)) ||
                 (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
                 free_allocs(al);
@@ -979,6 +988,23 @@ int exs_get_orientation_results(int64_t job, float* score, exs_pose_desc* desc) 
                 }
             }
         }
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_get_ranked_poses(int64_t job, int wait, int32_t* n_clusters, int32_t* ranked) {
+    try {
+        auto j = find_job(job);
+        if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+        const DockArgs& a = j->args;
+        if (a.rank_keep <= 0) return fail(EXS_EINVAL, "job %lld was run with rank_keep = 0", (long long)job);
+        if (int rc = job_wait(*j, wait)) return rc;
+        if (n_clusters)
+            if (int rc = copy_out(n_clusters, a.n_clusters, (size_t)j->L)) return rc;
+        if (ranked)
+            if (int rc = copy_out(ranked, a.ranked, (size_t)j->L * a.rank_keep)) return rc;
         return EXS_OK;
     } catch (const std::exception& e) {
         return fail(EXS_ENOMEM, "exception: %s", e.what());

@@ -128,6 +128,11 @@ struct DockArgs {
     double* topk_score64;     // [L*top_k]
     uint8_t* topk_theta;      // [R*top_k], element (rot_base+b)*top_k + t
     int32_t* topk_tau;        // [L*top_k]
+    // ranking of the final poses (rank_keep > 0)
+    float rank_thr2;          // RMSD threshold squared (A^2)
+    int32_t rank_keep;        // ranked poses kept per ligand
+    int32_t* n_clusters;      // [L]
+    int32_t* ranked;          // [L*rank_keep] orientation indices, leaders first
 };
 
 // Per-ligand LDS staging of a tile (topology read wave-uniformly by the search).

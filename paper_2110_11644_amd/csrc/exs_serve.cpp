@@ -210,6 +210,7 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     if (p.n_offsets != 1 && p.n_offsets != 27) return rt::fail(EXS_EINVAL, "n_offsets must be 1 or 27");
     if (p.passes < 0 || p.passes > 64) return rt::fail(EXS_EINVAL, "passes %d", p.passes);
     if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return rt::fail(EXS_EINVAL, "top_k %d", p.top_k);
+    if (p.rank_keep != 0) return rt::fail(EXS_EINVAL, "the server does not rank poses (rank_keep must be 0)");
     ppl_ = p.poses_per_lane ? p.poses_per_lane : 1;
     if (ppl_ != 1 && ppl_ != 2) return rt::fail(EXS_EINVAL, "poses_per_lane %d", ppl_);
     wpl_ = (K_ + kWave * ppl_ - 1) / (kWave * ppl_);
