@@ -2,7 +2,10 @@
 // launches over texel storage types.
 #include <math.h>
 
+#include <algorithm>
+
 #include "exs_internal.h"
+#include "rank_poses.inc"
 
 namespace exs {
 
@@ -160,6 +163,16 @@ hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int n
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(expand_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src,
                        static_cast<uint4*>(dst), nx, ny, nz, per_chan, count, storage);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st) {
+    if (n_lig <= 0) return hipSuccess;
+    // up to 4 waves (ligands) per block, within 64 KB of LDS
+    const size_t per_wave = (size_t)rank_lds_words(a.K) * sizeof(int);
+    const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
+    hipLaunchKernelGGL(rank_kernel, dim3((n_lig + waves - 1) / waves), dim3(waves * kWave),
+                       waves * per_wave, st, a, n_lig);
     return hipGetLastError();
 }
 

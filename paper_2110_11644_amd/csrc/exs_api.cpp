@@ -685,7 +685,9 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         a.n_queues = kXcds;
         hipError_t e = launch_zero_ints(a.tile_counter, kXcds, st);
         if (e != hipSuccess) return e;
-        return launch_dock(a, storage, ppl, resident, threads, lds, st);
+        e = launch_dock(a, storage, ppl, resident, threads, lds, st);
+        if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, st);
+        return e;
     }
     int start = 0;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -700,6 +702,7 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         if (e != hipSuccess) return e;
         start += gsz;
     }
+    if (base.rank_keep > 0) return launch_rank(base, b.L, st);
     return hipSuccess;
 }
 
@@ -852,6 +855,7 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 (rc = job_alloc(al, &a.topk_tau, (size_t)L * top_k)) ||
                 (rc = job_alloc(al, &a.n_clusters, (size_t)L)) ||
                 (rc = job_alloc(al, &a.ranked, (size_t)L * p.rank_keep)) ||
+                (rc = job_alloc(al, &a.final_xyz, p.rank_keep > 0 ? (size_t)A * 3 * K : (size_t)0)) ||
                 (rc = job_alloc(al, &a.tile_counter, (size_t)kXcds)) ||
                 (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
                 free_allocs(al);

@@ -133,7 +133,14 @@ struct DockArgs {
     int32_t rank_keep;        // ranked poses kept per ligand
     int32_t* n_clusters;      // [L]
     int32_t* ranked;          // [L*rank_keep] orientation indices, leaders first
+    float* final_xyz;         // [A*3][K] final pose of every orientation (rank_keep > 0)
 };
+
+// LDS words per wave of the ranking kernel: rank, state and score per pose, the leader bits,
+// the coordinates of 8 candidate leaders and their mutual distances.
+__host__ __device__ inline int rank_lds_words(int K) {
+    return 3 * K + (K + 31) / 32 + 8 * 3 * kMaxAtoms + 8 * 8;
+}
 
 // Per-ligand LDS staging of a tile (topology read wave-uniformly by the search).
 struct LigLds {
@@ -181,6 +188,8 @@ struct ResultRec {
 hipError_t launch_gather_results(const int32_t* lig, const int32_t* atom_dst, const int32_t* rot_dst,
                                  int n, const DockArgs& a, ResultRec* rec, float* coords,
                                  uint8_t* theta, hipStream_t st);
+// Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand.
+hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 hipError_t upload_trig_tables();
 const void* dock_kernel_fn(int storage, int S, int ppl);
