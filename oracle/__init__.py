@@ -82,6 +82,10 @@ def lib():
         L.orc_dock_batch.argtypes = [C.POINTER(_Grid), C.c_int, C.POINTER(_Params), C.c_int,
                                      _ip, _fp, _fp, _fp, _up, _ip, _ip, _ip, _ip, _ip,
                                      _ip, _dp, _dp, _ip, _ip, _ip, C.c_int]
+        L.orc_distance_sum.restype = C.c_double
+        L.orc_distance_sum.argtypes = [C.c_int, _dp]
+        L.orc_unfold_ligand.argtypes = [C.c_int, _fp, _fp, _fp, C.c_int, _ip, C.c_int, _ip,
+                                        C.c_int, C.c_int, C.c_double, _dp, _ip, _ip]
         L.orc_rmsd.restype = C.c_double
         L.orc_rmsd.argtypes = [C.c_int, _dp, _dp]
         L.orc_rank_poses.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double,
@@ -246,6 +250,27 @@ def dock_ligand(grid: Grid, params: Params, lig, coords: bool = False, trace_cap
     out["best_score"] = bs.value
     out["near_tie"] = out["near_tie"].astype(bool)
     return out
+
+
+def distance_sum(X: np.ndarray) -> float:
+    """Sum of the distances between all atom pairs of a pose [n,3] (Sec. 3.1, first step)."""
+    X = np.ascontiguousarray(X, np.float64)
+    return float(lib().orc_distance_sum(X.shape[0], _ptr(X, _dp)))
+
+
+def unfold_ligand(lig, torsion_steps: int, passes: int, tol: float = 1e-4) -> dict:
+    """Sec. 3.1, first step: turn the rotatable bonds (side without atom 0, S turns each, bonds
+    in list order, `passes` passes) to maximise the sum of interatomic distances.  Returns
+    xyz [n,3] (FP64, input frame), turns [passes, nrot] and the near-tie count."""
+    x, y, z, t, b, r = _lig_arrays(lig)
+    n, nr = x.size, r.size
+    X = np.zeros((n, 3))
+    turns = np.zeros((max(passes, 0), nr), np.int32)
+    nt = C.c_int()
+    _check(lib().orc_unfold_ligand(n, _ptr(x, _fp), _ptr(y, _fp), _ptr(z, _fp), b.size // 2,
+                                   _ptr(b, _ip), nr, _ptr(r, _ip), int(torsion_steps), int(passes),
+                                   float(tol), _ptr(X, _dp), _ptr(turns, _ip), C.byref(nt)))
+    return dict(xyz=X, turns=turns, near_ties=int(nt.value))
 
 
 def rmsd(a: np.ndarray, b: np.ndarray) -> float:

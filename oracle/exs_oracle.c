@@ -674,3 +674,74 @@ int orc_rank_poses(int K, int n, const double *poses, const double *scores, doub
     free(leaders);
     return nl;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Unfolding of the input conformation (first step of the method)           */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Sec. 3.1, first step: before docking, and independently of the protein, the
+ * ligand is flattened by turning its torsional bonds so that the sum of the
+ * distances between all its atoms is as large as possible.  The paper gives no
+ * procedure; the reading here mirrors the docking sweep: per pass, every
+ * rotatable bond in list order tries the S-1 relative turns 2*pi*s/S of the side
+ * without atom 0 and keeps the largest sum if strictly larger (ties keep the
+ * current shape, then the lower s).
+ */
+double orc_distance_sum(int n, const double *X)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dx = X[3 * i] - X[3 * j], dy = X[3 * i + 1] - X[3 * j + 1],
+                   dz = X[3 * i + 2] - X[3 * j + 2];
+            s += sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    return s;
+}
+
+/* Input conformation x, y, z (A), bonds, rotatable bonds.  Out: X_out [n*3] in the input
+ * frame (atom 0's side does not move), turns [passes*nrot] (the s kept per pass and bond),
+ * *near_ties = decisions where another turn's sum is within tol * max(D, 1) of the kept one. */
+int orc_unfold_ligand(int n, const float *x, const float *y, const float *z, int nb,
+                      const int *bij, int nrot, const int *rot_bond, int S, int passes,
+                      double tol, double *X_out, int *turns, int *near_ties)
+{
+    if (n < 1 || S < 1 || passes < 0 || !X_out) return ORC_EINVAL;
+    int *u = (int *)malloc(sizeof(int) * (size_t)(nrot > 0 ? nrot : 1));
+    int *v = (int *)malloc(sizeof(int) * (size_t)(nrot > 0 ? nrot : 1));
+    unsigned char *mv = (unsigned char *)malloc((size_t)(nrot > 0 ? nrot : 1) * n);
+    double *Y = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *cand = (double *)malloc(sizeof(double) * (size_t)S);
+    int rc = ORC_OK, nt = 0;
+    if (!u || !v || !mv || !Y || !cand) { rc = ORC_ENOMEM; goto done; }
+    for (int b = 0; b < nrot; ++b) {
+        rc = orc_moving_set(n, nb, bij, rot_bond[b], &u[b], &v[b], mv + (size_t)b * n);
+        if (rc) goto done;
+    }
+    for (int i = 0; i < n; ++i) {
+        X_out[3 * i] = (double)x[i]; X_out[3 * i + 1] = (double)y[i]; X_out[3 * i + 2] = (double)z[i];
+    }
+    for (int p = 0; p < passes; ++p)
+        for (int b = 0; b < nrot; ++b) {
+            cand[0] = orc_distance_sum(n, X_out);
+            for (int s = 1; s < S; ++s) {
+                memcpy(Y, X_out, sizeof(double) * 3 * (size_t)n);
+                orc_rotate_about_bond(n, Y, u[b], v[b], mv + (size_t)b * n, 2.0 * ORC_PI * s / S);
+                cand[s] = orc_distance_sum(n, Y);
+            }
+            int best = 0;
+            for (int s = 1; s < S; ++s)
+                if (cand[s] > cand[best]) best = s;
+            double m = fabs(cand[best]) > 1.0 ? fabs(cand[best]) : 1.0;
+            for (int s = 0; s < S; ++s)
+                if (s != best && cand[best] - cand[s] < tol * m) { ++nt; break; }
+            if (best != 0)
+                orc_rotate_about_bond(n, X_out, u[b], v[b], mv + (size_t)b * n, 2.0 * ORC_PI * best / S);
+            if (turns) turns[p * nrot + b] = best;
+        }
+done:
+    if (near_ties) *near_ties = nt;
+    free(u); free(v); free(mv); free(Y); free(cand);
+    return rc;
+}

@@ -551,3 +551,79 @@ def test_rank_poses_special_cases(oracle_lib):
     s2[[0, 9]] = np.nan                                          # NaN scores rank last
     r = O.rank_poses(poses, s2, 0.0)
     assert r["order"][-2:].tolist() == [0, 9]
+
+
+# ------------------------------------------------------------------------------------------------
+# Unfolding of the input conformation (Sec. 3.1, first step)
+
+
+def test_distance_sum_closed_forms(oracle_lib):
+    O = oracle_lib
+    a = 1.7
+    tri = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * np.sqrt(3) / 2, 0]])
+    assert abs(O.distance_sum(tri) - 3 * a) < 1e-12
+    tet = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)   # edge 2 sqrt 2
+    assert abs(O.distance_sum(tet) - 6 * 2 * np.sqrt(2)) < 1e-12
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(9, 3))
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    assert abs(O.distance_sum(X @ Q.T + [3, -1, 2]) - O.distance_sum(X)) < 1e-10
+    assert O.distance_sum(X[:1]) == 0.0
+
+
+class _Lig:
+    def __init__(self, xyz, bonds, rot):
+        self.xyz = np.asarray(xyz, np.float32)
+        self.types = np.zeros(len(xyz), np.uint8)
+        self.bonds = np.asarray(bonds, np.int32)
+        self.rot = np.asarray(rot, np.int32)
+
+
+def test_unfold_turns_an_all_cis_chain_all_trans(oracle_lib):
+    """A planar all-cis 5-chain with its two inner bonds rotatable unfolds to the planar
+    zig-zag: every distance is the all-trans closed form (d15 = 2 d13)."""
+    O = oracle_lib
+    gold = _golden_chain()
+    cis = planar_chain(5, cis=True)
+    trans = planar_chain(5, cis=False)
+    lig = _Lig(cis, chain_bonds(5), [1, 2])
+    r = O.unfold_ligand(lig, 8, 2)
+    X = r["xyz"]
+    D = np.linalg.norm(X[:, None] - X[None], axis=-1)
+    T = np.linalg.norm(trans[:, None] - trans[None], axis=-1)
+    assert np.abs(D - T).max() < 1e-5                      # the input is float32
+    assert abs(D[0, 4] - gold["d15_trans"]) < 1e-5
+    assert r["turns"][0].tolist() == [4, 4]                  # half turns, then nothing to gain
+    assert r["turns"][1].tolist() == [0, 0]
+    assert abs(O.distance_sum(X) - O.distance_sum(trans)) < 1e-4
+
+
+def test_unfold_keeps_geometry_and_never_shrinks(oracle_lib):
+    O = oracle_lib
+    for lig in S.make_ligands("batched", 3, 6):
+        X0 = lig.xyz.astype(np.float64)
+        r = O.unfold_ligand(lig, 16, 2)
+        X = r["xyz"]
+        assert O.distance_sum(X) >= O.distance_sum(X0) - 1e-9
+        bl0 = np.linalg.norm(X0[lig.bonds[:, 0]] - X0[lig.bonds[:, 1]], axis=1)
+        bl = np.linalg.norm(X[lig.bonds[:, 0]] - X[lig.bonds[:, 1]], axis=1)
+        assert np.abs(bl - bl0).max() < 1e-9
+        _, _, moving = O.rot_topology(lig.n, lig.bonds, lig.rot)
+        still = ~moving.any(axis=0) if len(lig.rot) else np.ones(lig.n, bool)
+        assert np.array_equal(X[still], X0[still])         # atom 0's side never moves
+
+
+def test_unfold_converges_to_a_single_bond_optimum(oracle_lib):
+    """After enough passes no single turn of any rotatable bond increases the distance sum."""
+    O = oracle_lib
+    S_ = 16
+    for lig in S.make_ligands("batched", 4, 3):
+        r = O.unfold_ligand(lig, S_, 40)
+        X = r["xyz"]
+        assert not r["turns"][-1].any()
+        u, v, moving = O.rot_topology(lig.n, lig.bonds, lig.rot)
+        D = O.distance_sum(X)
+        for b in range(len(lig.rot)):
+            for s in range(1, S_):
+                Y = O.rotate_about_bond(X, u[b], v[b], moving[b], 2 * np.pi * s / S_)
+                assert O.distance_sum(Y) <= D + 1e-9
