@@ -499,6 +499,8 @@ def main():
     ap.add_argument("--rank-keep", type=int, default=0,
                     help="scale/small: rank each ligand's final poses and keep this many (0 = off)")
     ap.add_argument("--cluster-rmsd", type=float, default=3.0, help="ranking: RMSD threshold (A)")
+    ap.add_argument("--unfold-passes", type=int, default=0,
+                    help="scale/small: unfold the ligands first (passes; 0 = off), timed apart")
     ap.add_argument("--requests", type=int, default=2000, help="serving: timed requests")
     ap.add_argument("--sweep", default="0.5,0.9", help="serving: other offered loads to serve")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
@@ -553,6 +555,12 @@ def main():
     bid = B.exs_upload_ligands(batch, pocket_ids=[pid], stream=stream)
     torch.cuda.synchronize()
     upload_s = time.perf_counter() - t_up
+    unfold_ms = None
+    if args.unfold_passes > 0:        # first step of the method, once per uploaded batch
+        t_uf = time.perf_counter()
+        B.exs_unfold_ligands(bid, s.torsion_steps, args.unfold_passes, stream=stream)
+        unfold_ms = (time.perf_counter() - t_uf) * 1e3
+        progress("unfolded %d ligands (%d passes): %.2f ms" % (batch.n_ligands, args.unfold_passes, unfold_ms))
     flags = B.EXS_FLAG_PERSISTENT if args.persistent else 0
     prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                           s.clash_cutoff, s.clash_penalty, top_k=0, poses_per_lane=args.ppl,
@@ -619,6 +627,7 @@ def main():
             "ligands": L, "atoms": A, "parallelism": "single GPU",
             "poses_per_lane": args.ppl, "ligands_per_wg": args.lpw,
             "rank_keep": args.rank_keep, "cluster_rmsd_A": args.cluster_rmsd if args.rank_keep else None,
+            "unfold_passes": args.unfold_passes, "unfold_ms": None if unfold_ms is None else round(unfold_ms, 3),
         },
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -85,6 +85,27 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
                          int values_on_device, void* stream, int32_t* pocket_id_out);
 
 /*
+ * Unfold the uploaded ligands in place before docking (Sec. 3.1, first step: the
+ * ligand is flattened, independently of the protein, by turning its torsional
+ * bonds so that the sum of the distances between all its atoms grows).  Per
+ * pass, every rotatable bond in list order tries the S-1 relative turns
+ * 2*pi*s/S (S = torsion_steps: 8, 16 or 32) of the side without atom 0 and
+ * keeps the largest distance sum if strictly larger (ties keep the shape, then
+ * the lower s); `passes` passes (0..64).  FP32 on the device; a ligand whose
+ * shape changed is then re-centred on its centroid (the docking places that
+ * centroid at the pocket centre), one that kept its shape is left as uploaded.  Runs on `stream` and waits for it; order it
+ * before any docking of the batch.
+ *   turns_out  [passes * R] kept turn s per pass and rotatable bond (the
+ *              batch's bonds in CSR order), or NULL.
+ * Errors: EXS_EINVAL (torsion_steps, passes, device), EXS_ENOENT, EXS_EDEVICE.
+ */
+int exs_unfold_ligands(int64_t batch, int torsion_steps, int passes, void* stream,
+                       int32_t* turns_out);
+
+/* The batch's current coordinates [A][3] (centred on each ligand's centroid), to host. */
+int exs_get_ligand_coords(int64_t batch, float* xyz);
+
+/*
  * Ranked poses of a job run with rank_keep > 0 (Sec. 3.1, third step: cluster
  * leaders first, then the other poses, each by score).
  *   n_clusters  [L] clusters (leaders) per ligand, or NULL

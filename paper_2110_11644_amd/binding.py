@@ -26,7 +26,8 @@ STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
 # exported symbols (kept in step with include/exs.h)
 SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
            "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
-           "exs_get_orientation_results", "exs_get_ranked_poses", "exs_job_elapsed_ms",
+           "exs_get_orientation_results", "exs_get_ranked_poses", "exs_unfold_ligands",
+           "exs_get_ligand_coords", "exs_job_elapsed_ms",
            "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
            "exs_server_destroy")
@@ -98,6 +99,8 @@ def lib():
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
         L.exs_get_ranked_poses.argtypes = [i64, C.c_int, vp, vp]
+        L.exs_unfold_ligands.argtypes = [i64, C.c_int, C.c_int, vp, vp]
+        L.exs_get_ligand_coords.argtypes = [i64, vp]
         L.exs_gather_probe.argtypes = [i32, i64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_uint32, vp,
                                        C.POINTER(C.c_float), C.POINTER(C.c_double)]
         L.exs_server_create.argtypes = [vp, C.c_int, C.POINTER(exs_search_params),
@@ -245,6 +248,22 @@ def exs_get_orientation_results(job: int, n_ligands: int, n_orient: int) -> dict
     desc = np.zeros(n_ligands * n_orient, POSE_DESC)
     _check(lib().exs_get_orientation_results(int(job), _p(sc), _p(desc)))
     return dict(score=sc.reshape(n_ligands, n_orient), desc=desc.reshape(n_ligands, n_orient))
+
+
+def exs_unfold_ligands(batch_id: int, torsion_steps: int, passes: int, n_rot: int = 0,
+                       stream=None):
+    """Unfold the uploaded batch in place; returns the kept turns [passes, n_rot] when
+    n_rot (the batch's rotatable bond count) is given, else None."""
+    turns = np.zeros((passes, n_rot), np.int32) if n_rot > 0 and passes > 0 else None
+    _check(lib().exs_unfold_ligands(int(batch_id), int(torsion_steps), int(passes), _stream(stream),
+                                    _p(turns) if turns is not None else None))
+    return turns
+
+
+def exs_get_ligand_coords(batch_id: int, n_atoms: int) -> np.ndarray:
+    xyz = np.zeros((n_atoms, 3), np.float32)
+    _check(lib().exs_get_ligand_coords(int(batch_id), _p(xyz)))
+    return xyz
 
 
 def exs_get_ranked_poses(job: int, n_ligands: int, rank_keep: int, wait: bool = True):

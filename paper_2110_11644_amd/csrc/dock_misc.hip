@@ -6,6 +6,7 @@
 
 #include "exs_internal.h"
 #include "rank_poses.inc"
+#include "unfold.inc"
 
 namespace exs {
 
@@ -173,6 +174,23 @@ hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st) {
     const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     hipLaunchKernelGGL(rank_kernel, dim3((n_lig + waves - 1) / waves), dim3(waves * kWave),
                        waves * per_wave, st, a, n_lig);
+    return hipGetLastError();
+}
+
+hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
+                         const uint4* rot_mask, int32_t* turns, int n_lig, int R, int S, int passes,
+                         hipStream_t st) {
+    if (n_lig <= 0) return hipSuccess;
+    UnfoldArgs a{info, ref, ref64, rot_uv, rot_mask, turns, n_lig, R, passes, 0};
+    constexpr int kWavesPerBlock = 4;
+    const dim3 grid((n_lig + kWavesPerBlock - 1) / kWavesPerBlock), block(kWavesPerBlock * kWave);
+    const size_t lds = (size_t)kWavesPerBlock * kMaxAtoms * sizeof(float4);
+    switch (S) {
+        case 8: hipLaunchKernelGGL(unfold_kernel<8>, grid, block, lds, st, a); break;
+        case 16: hipLaunchKernelGGL(unfold_kernel<16>, grid, block, lds, st, a); break;
+        case 32: hipLaunchKernelGGL(unfold_kernel<32>, grid, block, lds, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1024,6 +1024,49 @@ int exs_job_elapsed_ms(int64_t job, float* ms) {
     return EXS_OK;
 }
 
+int exs_unfold_ligands(int64_t batch, int torsion_steps, int passes, void* stream, int32_t* turns_out) {
+    try {
+        if (torsion_steps != 8 && torsion_steps != 16 && torsion_steps != 32)
+            return fail(EXS_EINVAL, "torsion_steps %d: supported 8, 16, 32", torsion_steps);
+        if (passes < 0 || passes > 64) return fail(EXS_EINVAL, "passes %d outside [0, 64]", passes);
+        auto b = find_batch(batch);
+        if (!b) return fail(EXS_ENOENT, "unknown ligand batch %lld", (long long)batch);
+        int dev;
+        if (int rc = current_device(&dev)) return rc;
+        if (dev != b->device) return fail(EXS_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+        hipStream_t st = (hipStream_t)stream;
+        int32_t* d_turns = nullptr;
+        const size_t nt = (size_t)passes * b->R;
+        if (turns_out && nt > 0) HIP_TRY(hipMalloc(&d_turns, nt * sizeof(int32_t)));
+        hipError_t e = launch_unfold(b->d_info, b->d_ref, b->d_ref64, b->d_rot_uv, b->d_rot_mask,
+                                     d_turns, b->L, b->R, torsion_steps, passes, st);
+        if (e == hipSuccess && d_turns)
+            e = hipMemcpyAsync(turns_out, d_turns, nt * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (d_turns) (void)hipFree(d_turns);
+        if (e != hipSuccess) return fail(EXS_EDEVICE, "unfold: %s", hipGetErrorString(e));
+        return EXS_OK;
+    } catch (const std::exception& ex) {
+        return fail(EXS_ENOMEM, "exception: %s", ex.what());
+    }
+}
+
+int exs_get_ligand_coords(int64_t batch, float* xyz) {
+    try {
+        if (!xyz) return fail(EXS_EINVAL, "null argument");
+        auto b = find_batch(batch);
+        if (!b) return fail(EXS_ENOENT, "unknown ligand batch %lld", (long long)batch);
+        std::vector<float4> r((size_t)b->A);
+        if (b->A > 0) HIP_TRY(hipMemcpy(r.data(), b->d_ref, r.size() * sizeof(float4), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < r.size(); ++i) {
+            xyz[3 * i] = r[i].x; xyz[3 * i + 1] = r[i].y; xyz[3 * i + 2] = r[i].z;
+        }
+        return EXS_OK;
+    } catch (const std::exception& ex) {
+        return fail(EXS_ENOMEM, "exception: %s", ex.what());
+    }
+}
+
 int exs_gather_probe(int32_t pocket_id, int64_t n_lanes, int lookups_per_lane, int batch,
                      float half_edge_A, float walk_step_A, uint32_t seed, void* stream,
                      float* ms_out, double* checksum_out) {

@@ -188,6 +188,11 @@ struct ResultRec {
 hipError_t launch_gather_results(const int32_t* lig, const int32_t* atom_dst, const int32_t* rot_dst,
                                  int n, const DockArgs& a, ResultRec* rec, float* coords,
                                  uint8_t* theta, hipStream_t st);
+// Unfolding of `n_lig` packed ligands in place (ref, ref64), S turns per bond, `passes` passes;
+// turns [passes * R] receives the kept turns (or null).
+hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
+                         const uint4* rot_mask, int32_t* turns, int n_lig, int R, int S, int passes,
+                         hipStream_t st);
 // Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand.
 hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
