@@ -1,0 +1,122 @@
+"""Parity at full size, in the launch configurations the benchmark times.
+
+scale: 10,000 ligands x one 96^3 x 8 pocket, K=256, S=32, P=2, T=27, one launch per pocket;
+batched: 100,000 ligands over 15 pockets, one persistent launch replayed from a graph.  A
+seeded sample of ligands is checked against the FP64 oracle (full per-orientation acceptance
+for scale; best pose for batched, where fetching every orientation of 100,000 ligands is not
+needed), and properties that hold at any size are checked on every ligand: finite scores, the
+best score is the minimum of the ligand's orientation scores (scale) and equals its descriptor's
+FP32 score, descriptors in range."""
+import sys
+
+import numpy as np
+import pytest
+
+import exs_synth as S
+from parity import check_ligand, gpu_desc_to_theta_tau, tol, RMSD_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2110_11644_amd import binding
+    binding.lib()
+    return binding
+
+
+def descriptors_in_range(batch, desc, s):
+    nrot = np.diff(batch.rot_offset)
+    assert np.all(desc["orient"] >= 0) and np.all(desc["orient"] < s.n_orient)
+    assert np.all(desc["n_rot"] == nrot)
+    assert np.all(np.abs(desc["tau"].astype(int)) <= s.passes)
+    assert np.all(desc["theta"] < s.torsion_steps)
+
+
+def test_scale_workload_full_size(B, oracle_lib):
+    O = oracle_lib
+    wl, s = S.SCALE, S.SCALE.search
+    pocket = S.make_pocket(wl, 0)
+    batch = S.make_ligand_batch(wl, 0)
+    L, A = batch.n_ligands, int(batch.atom_offset[-1])
+    log("scale full size: %d ligands, %d atoms" % (L, A))
+    pid = B.exs_load_pocket_grid(pocket.values, pocket.spacing, pocket.origin)
+    try:
+        bid = B.exs_upload_ligands(batch, pocket_ids=[pid])
+        prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                              s.clash_cutoff, s.clash_penalty)
+        job = B.exs_dock_batch(bid, prm)
+        best = B.exs_get_best_poses(job, L, A)
+        orient = B.exs_get_orientation_results(job, L, s.n_orient)
+        B.exs_release_job(job)
+        B.exs_release_ligands(bid)
+    finally:
+        B.exs_unload_pocket(pid)
+    sc = orient["score"]
+    assert np.all(np.isfinite(sc)) and np.all(np.isfinite(best["best_score"]))
+    assert np.array_equal(best["best_score"], sc.min(axis=1))
+    assert np.array_equal(best["desc"]["orient"], sc.argmin(axis=1))
+    descriptors_in_range(batch, best["desc"], s)
+    rng = np.random.default_rng(20211011)
+    sample = sorted(rng.choice(L, size=5, replace=False).tolist())
+    g, p = O.Grid.of(pocket), O.Params.of(s)
+    stats = {}
+    for l in sample:
+        lig = batch.ligand(l)
+        a0, a1 = int(batch.atom_offset[l]), int(batch.atom_offset[l + 1])
+        check_ligand(O, g, p, lig, sc[l], orient["desc"][l], best["best_score"][l], best["desc"][l],
+                     best["coords"][a0:a1], stats=stats)
+    log("scale sample %s: %s" % (sample, stats))
+
+
+def test_batched_workload_full_size(B, oracle_lib):
+    O = oracle_lib
+    wl, s = S.BATCHED, S.BATCHED.search
+    pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+    batch = S.make_ligand_batch(wl, 0)
+    L, A = batch.n_ligands, int(batch.atom_offset[-1])
+    log("batched full size: %d ligands over %d pockets" % (L, len(pockets)))
+    pids = [B.exs_load_pocket_grid(pk.values, pk.spacing, pk.origin) for pk in pockets]
+    try:
+        bid = B.exs_upload_ligands(batch, pocket_ids=pids)
+        prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                              s.clash_cutoff, s.clash_penalty, poses_per_lane=1, ligands_per_wg=1,
+                              flags=B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH)
+        job = B.exs_dock_batch(bid, prm)
+        best = B.exs_get_best_poses(job, L, A)
+        B.exs_release_job(job)
+        B.exs_release_ligands(bid)
+    finally:
+        for pid in pids:
+            B.exs_unload_pocket(pid)
+    assert np.all(np.isfinite(best["best_score"]))
+    assert np.array_equal(best["best_score"], best["desc"]["score"])
+    descriptors_in_range(batch, best["desc"], s)
+    rng = np.random.default_rng(20211012)
+    sample = sorted(rng.choice(L, size=5, replace=False).tolist())
+    p = O.Params.of(s)
+    for l in sample:
+        lig = batch.ligand(l)
+        g = O.Grid.of(pockets[lig.pocket])
+        d = best["desc"][l]
+        th, ta = gpu_desc_to_theta_tau(d, len(lig.rot))
+        k = int(d["orient"])
+        e, _, amb, X = O.rescore_desc(g, p, lig, k, th, ta)
+        assert abs(float(best["best_score"][l]) - e) <= tol(e) + p.clash_penalty * amb
+        a0, a1 = int(batch.atom_offset[l]), int(batch.atom_offset[l + 1])
+        rmsd = float(np.sqrt(np.mean(np.sum((best["coords"][a0:a1].astype(np.float64) - X) ** 2, axis=1))))
+        assert rmsd <= RMSD_TOL
+        ref = O.dock_ligand(g, p, lig)
+        kr = int(ref["best_k"])
+        if abs(float(best["best_score"][l]) - ref["best_score"]) > tol(ref["best_score"]):
+            assert ref["near_tie"][k] or ref["near_tie"][kr], "ligand %d: best %.7g vs oracle %.7g" % (
+                l, best["best_score"][l], ref["best_score"])
+        log("batched ligand %d: gpu %.6f (k=%d) oracle %.6f (k=%d)" % (
+            l, best["best_score"][l], k, ref["best_score"], kr))
