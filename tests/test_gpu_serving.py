@@ -143,3 +143,46 @@ def test_request_larger_than_the_arena_is_refused(B, setup):
         assert ei.value.code == B.EXS_ENOMEM
     finally:
         B.exs_server_destroy(srv)
+
+
+def test_concurrent_submitters_equal_one_batch(B, setup):
+    """A campaign-style stream: chunks submitted from three host threads at once (each packs
+    its chunk) give, ligand for ligand, the results of one batch docked in a single launch."""
+    pids, _ = setup
+    ligs = S.make_ligands(WL, 500, 240)
+    rng = np.random.default_rng(9)
+    for l in ligs:
+        l.pocket = int(rng.integers(0, 3))
+    whole = S.batch_from_ligands(ligs)
+    ref = alone(B, pids, whole)
+    chunks = [S.batch_from_ligands(ligs[a:a + 30]) for a in range(0, len(ligs), 30)]
+    srv = B.exs_server_create(pids, params(B))
+    try:
+        ids = [None] * len(chunks)
+        nxt = [0]
+        lock = threading.Lock()
+
+        def packer():
+            while True:
+                with lock:
+                    i = nxt[0]
+                    nxt[0] += 1
+                if i >= len(chunks):
+                    return
+                ids[i] = B.exs_server_submit(srv, chunks[i], pocket_ids=pids)
+        th = [threading.Thread(target=packer) for _ in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        got = [B.exs_server_poll(srv, ids[i], c.n_ligands, int(c.atom_offset[-1]))
+               for i, c in enumerate(chunks)]
+    finally:
+        B.exs_server_destroy(srv)
+    best = np.concatenate([g["best_score"] for g in got])
+    desc = np.concatenate([g["desc"] for g in got])
+    xyz = np.concatenate([g["coords"] for g in got])
+    assert np.array_equal(best, ref["best_score"])
+    assert np.array_equal(desc["orient"], ref["desc"]["orient"])
+    assert np.array_equal(desc["theta"], ref["desc"]["theta"])
+    assert np.array_equal(xyz, ref["coords"])
