@@ -152,6 +152,22 @@ def test_brute_force_tiny_ligands_on_gpu(B, oracle_lib, small):
                 assert out["best"][l]["theta"][:len(lig.rot)].tolist() == r["theta"][k].tolist()
 
 
+def test_degenerate_ligands_and_one_orientation(B, oracle_lib, small):
+    """Single-atom and two-atom ligands (no pairs to clash, no rotatable bond), a ligand whose
+    rotatable bond turns one atom, and K = 1 (one restart): full acceptance against the oracle."""
+    O = oracle_lib
+    p, g, _ = small
+    ligs = [Lig([[0.3, -0.2, 0.1]], [2], np.zeros((0, 2), np.int32)),
+            Lig([[0, 0, 0], [1.5, 0, 0]], [0, 3], [[0, 1]]),
+            Lig([[0, 0, 0], [1.5, 0, 0], [2.0, 1.4, 0], [3.5, 1.4, 0.2]], [1, 2, 3, 0],
+                [[0, 1], [1, 2], [2, 3]], [1])]
+    batch = S.batch_from_ligands(ligs)
+    for s in (S.SearchSettings(8, 8, 1, 27), S.SearchSettings(1, 16, 2, 27), S.SearchSettings(64, 32, 1, 1)):
+        log("degenerate ligands, K=%d S=%d P=%d T=%d" % (s.n_orient, s.torsion_steps, s.passes, s.n_offsets))
+        out = run(B, [p], batch, s)
+        check_all(O, [g], O.Params.of(s), batch, out)
+
+
 def test_largest_ligands_use_all_mask_words(B, oracle_lib, small):
     """n = 128 atoms and 32 rotatable bonds (the limits): every 32-bit word of the masks."""
     O = oracle_lib
