@@ -213,7 +213,11 @@ def run_batched(args, torch, S, B):
     flags = B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH
     ppl, lpw, tuned = args.ppl or 1, args.lpw or 1, None
     if args.tune:
-        sample = batch.subset(range(0, L, max(1, L // 4096)))
+        # a sample that keeps the full run's work-queue layout: pockets holding more ligands
+        # than the device has in flight (3,072 waves) are scheduled pocket by pocket
+        inflight = 3072 // -(-s.n_orient // 64)
+        n_sample = min(L, max(4096, 2 * inflight * len(pids)))
+        sample = batch.subset(range(0, L, max(1, L // n_sample)))
         sid = B.exs_upload_ligands(sample, pocket_ids=pids, stream=stream)
         tuned = autotune.tune(sid, s, storage, B.EXS_FLAG_PERSISTENT,
                               float(np.diff(sample.atom_offset).mean()), use_cache=False,

@@ -157,6 +157,7 @@ struct Batch {
     std::mutex order_mu;
     std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
     std::map<std::vector<int>, std::vector<int>> group_sizes;
+    std::map<std::vector<int>, int> queue_counts;   // persistent orders: work queues
     std::map<std::vector<int64_t>, std::shared_ptr<Plan>> plans;   // graph plans by settings
 };
 
@@ -546,18 +547,18 @@ int exs_release_ligands(int64_t batch) {
 namespace {
 
 // Processing order.  Per-pocket launches: grouped by pocket, longest first in each group.
-// Persistent launch: pocket-major, cut into kXcds contiguous queues of equal cost, each
-// sorted longest first; queue q (run first by the workgroups of XCD q) then touches few
-// pockets, so each XCD's L2 holds few grids.  The device array holds the order followed
-// by the kXcds + 1 queue bounds.
+// Persistent launch: work queues laid out by queue_plan (spread or pocket-major); the device
+// array holds the order followed by the queue bounds (kMaxWorkQueues + 1 entries reserved) and
+// *n_queues receives their count.
 int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_t st,
-                int32_t** d_order, std::vector<int>* groups) {
+                int32_t** d_order, std::vector<int>* groups, int* n_queues) {
     std::vector<int> key = {K, S, P, T, persistent};
     std::lock_guard<std::mutex> lk(b.order_mu);
     auto it = b.d_orders.find(key);
     if (it != b.d_orders.end()) {
         *d_order = it->second;
         *groups = b.group_sizes[key];
+        *n_queues = b.queue_counts[key];
         return EXS_OK;
     }
     std::vector<double> cost(b.L);
@@ -571,9 +572,15 @@ int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_
     if (persistent) {
         std::vector<int> pocket(b.L);
         for (int l = 0; l < b.L; ++l) pocket[l] = b.info[l].pocket;
-        ord.resize(b.L + kXcds + 1);
-        xcd_queues(b.L, pocket.data(), cost.data(), kXcds, ord.data(), ord.data() + b.L);
+        int used = 0;
+        std::vector<int> seen(n_slots, 0);
+        for (int p : pocket) used += seen[p]++ == 0 ? 1 : 0;
+        const QueuePlan plan = queue_plan(b.L, used, (K + kWave - 1) / kWave);
+        ord.resize(b.L + kMaxWorkQueues + 1);
+        work_queues(b.L, pocket.data(), cost.data(), plan.n_queues, plan.pocket_major, ord.data(),
+                    ord.data() + b.L);
         groups->assign(1, b.L);
+        *n_queues = plan.n_queues;
     } else {
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
             if (b.info[a].pocket != b.info[c].pocket) return b.info[a].pocket < b.info[c].pocket;
@@ -590,6 +597,7 @@ int batch_order(Batch& b, int K, int S, int P, int T, int persistent, hipStream_
     }
     b.d_orders[key] = d;
     b.group_sizes[key] = *groups;
+    b.queue_counts[key] = *n_queues;
     *d_order = d;
     return EXS_OK;
 }
@@ -672,8 +680,8 @@ namespace {
 // The launch sequence of one job on `st`: a counter reset and one persistent dock
 // launch, or one dock launch per pocket group.
 hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<int>& groups,
-                        const int32_t* d_order, int storage, int ppl, bool persistent, int resident,
-                        int threads, size_t lds, hipStream_t st) {
+                        const int32_t* d_order, int n_queues, int storage, int ppl, bool persistent,
+                        int resident, int threads, size_t lds, hipStream_t st) {
     if (b.L == 0) return hipSuccess;
     if (persistent) {
         DockArgs a = base;
@@ -682,8 +690,8 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         a.n_tiles = (b.L + a.lpw - 1) / a.lpw;
         a.persistent = 1;
         a.queue_bounds = d_order + b.L;
-        a.n_queues = kXcds;
-        hipError_t e = launch_zero_ints(a.tile_counter, kXcds, st);
+        a.n_queues = n_queues;
+        hipError_t e = launch_zero_ints(a.tile_counter, n_queues, st);
         if (e != hipSuccess) return e;
         e = launch_dock(a, storage, ppl, resident, threads, lds, st);
         if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, st);
@@ -762,8 +770,9 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         if (int rc = orientation_tables(dev, K, &r32, &r64)) return rc;
         int32_t* d_order = nullptr;
         std::vector<int> groups;
+        int n_queues = 1;
         if (int rc = batch_order(*b, K, p.torsion_steps, p.passes, p.n_offsets, persistent, st,
-                                 &d_order, &groups)) return rc;
+                                 &d_order, &groups, &n_queues)) return rc;
 
         auto j = std::make_shared<Job>();
         j->device = dev; j->batch = b; j->prm = p; j->stream = st;
@@ -856,7 +865,7 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 (rc = job_alloc(al, &a.n_clusters, (size_t)L)) ||
                 (rc = job_alloc(al, &a.ranked, (size_t)L * p.rank_keep)) ||
                 (rc = job_alloc(al, &a.final_xyz, p.rank_keep > 0 ? (size_t)A * 3 * K : (size_t)0)) ||
-                (rc = job_alloc(al, &a.tile_counter, (size_t)kXcds)) ||
+                (rc = job_alloc(al, &a.tile_counter, (size_t)kMaxWorkQueues)) ||
                 (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
                 free_allocs(al);
                 return rc;
@@ -868,8 +877,8 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
                 hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    e = enqueue_dock(a, *b, groups, d_order, storage, ppl, persistent, resident,
-                                     threads, lds, cs);
+                    e = enqueue_dock(a, *b, groups, d_order, n_queues, storage, ppl, persistent,
+                                     resident, threads, lds, cs);
                     hipGraph_t gr = nullptr;
                     hipError_t e2 = hipStreamEndCapture(cs, &gr);
                     if (e == hipSuccess) e = e2;
@@ -897,8 +906,8 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         if (j->plan) {
             HIP_TRY(hipGraphLaunch(j->plan->exec, st));
         } else {
-            HIP_TRY(enqueue_dock(j->args, *b, groups, d_order, storage, ppl, persistent, resident,
-                                 threads, lds, st));
+            HIP_TRY(enqueue_dock(j->args, *b, groups, d_order, n_queues, storage, ppl, persistent,
+                                 resident, threads, lds, st));
         }
         HIP_TRY(hipEventRecord(j->ev1, st));
         std::lock_guard<std::mutex> lk(g_reg_mu);

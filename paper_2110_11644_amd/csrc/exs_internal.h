@@ -15,6 +15,30 @@ constexpr int kMaxWavesPerWg = 8;
 constexpr int kMaxThreadsPerWg = kMaxWavesPerWg * kWave;
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 
+// Work queues of a persistent launch: the workgroups of XCD x start on queue x % n_queues and
+// move on to the others once it is drained.  Two layouts of the order:
+//  * spread: kXcds queues, contiguous pocket-major runs of equal cost, each longest first.  For
+//    launches whose pockets hold fewer ligands each than the device has in flight: all of the
+//    launch runs at once and its tail decides (serving iterations of <= 4,096 ligands over 15
+//    pockets: capacity 152k docks/s, against 127k pocket by pocket).
+//  * pocket-major: kPocketMajorQueues queues, each pocket by pocket, longest first within a
+//    pocket, so that few pockets are in use at a time and their texel blocks stay in the L2s and
+//    the shared last-level cache (100,000 ligands over 15 pockets, FP32: 634 ms spread; 567,
+//    543, 548 ms with 1, 2, 4 pocket-major queues).
+constexpr int kMaxWorkQueues = kXcds;
+constexpr int kPocketMajorQueues = 2;
+constexpr int kInflightWaves = 256 * 4 * 3;   // CUs x SIMDs x dock-kernel waves per SIMD
+struct QueuePlan {
+    int n_queues;
+    bool pocket_major;
+};
+// Layout for n_ligands ligands over n_pockets distinct pockets, waves_per_ligand waves each.
+inline QueuePlan queue_plan(int64_t n_ligands, int n_pockets, int waves_per_ligand) {
+    const int64_t inflight = kInflightWaves / (waves_per_ligand > 0 ? waves_per_ligand : 1);
+    if (n_pockets >= 2 && n_ligands >= inflight * n_pockets) return {kPocketMajorQueues, true};
+    return {kXcds, false};
+}
+
 // Turn tables: for S in {8, 16, 32}, cos then sin of 2*pi*s/S at offset trig_offset(S).
 constexpr int kTrigEntries = 2 * (8 + 16 + 32);
 __host__ __device__ constexpr int trig_offset(int S) { return S == 8 ? 0 : (S == 16 ? 16 : 48); }
@@ -87,7 +111,7 @@ struct DockArgs {
     const uint4* excl;        // [A] bit j: pair (i, j) excluded (bond distance <= 3, or i == j)
     const uint32_t* rot_uv;   // [R] u | v << 16, u on atom 0's side
     const uint4* rot_mask;    // [R] atoms that turn with the bond
-    const int32_t* order;     // ligands in processing order (longest first)
+    const int32_t* order;     // ligands in processing order (pocket-major, longest first within)
     int32_t n_order;          // ligands in this launch
     int32_t n_tiles;          // ceil(n_order / lpw)
     // pockets
@@ -109,8 +133,8 @@ struct DockArgs {
     int64_t slot_floats;
     int32_t* tile_counter;    // persistent launches: next tile of each queue [n_queues]
     // persistent launches: n_queues + 1 positions in `order`, queue q = [qb[q], qb[q+1]);
-    // a workgroup takes tiles from the queue of its XCD first, then from the others.
-    // Null: one queue over the whole order.
+    // a workgroup takes tiles from queue (its XCD index mod n_queues) first, then from the
+    // others.  Null, or n_queues = 1: one queue over the whole order.
     const int32_t* queue_bounds;
     int32_t n_queues;
     int32_t pad1;

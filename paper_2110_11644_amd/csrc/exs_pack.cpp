@@ -149,8 +149,8 @@ double ligand_cost(int n, const int16_t* m, int nrot, int K, int S, int P, int T
     return (double)K * (look * 40.0 + pairs * 20.0);
 }
 
-void xcd_queues(int n, const int* pocket, const double* cost, int n_queues, int32_t* order,
-                int32_t* bounds) {
+void work_queues(int n, const int* pocket, const double* cost, int n_queues, bool pocket_major,
+                 int32_t* order, int32_t* bounds) {
     std::vector<int32_t> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
@@ -167,9 +167,10 @@ void xcd_queues(int n, const int* pocket, const double* cost, int n_queues, int3
         acc += cost[ord[i]];
         while (q < n_queues && acc >= total * q / n_queues) bounds[q++] = i + 1;
     }
-    for (int r = 0; r < n_queues; ++r)
-        std::stable_sort(ord.begin() + bounds[r], ord.begin() + bounds[r + 1],
-                         [&](int a, int c) { return cost[a] > cost[c]; });
+    if (!pocket_major)
+        for (int r = 0; r < n_queues; ++r)
+            std::stable_sort(ord.begin() + bounds[r], ord.begin() + bounds[r + 1],
+                             [&](int a, int c) { return cost[a] > cost[c]; });
     std::copy(ord.begin(), ord.end(), order);
 }
 

@@ -42,10 +42,11 @@ int pack_ligand(int n, const int32_t* bond_ij, int nb, const int32_t* rot_bond, 
 // m[b] = atoms that turn with rotatable bond b.
 double ligand_cost(int n, const int16_t* m, int nrot, int K, int S, int P, int T);
 
-// Work queues of a persistent launch, one per XCD: items (ligands) ordered pocket-major, cut
-// into n_queues contiguous ranges of equal total cost, each range longest first.  order[0..n)
-// receives item indices, bounds[0..n_queues] the range starts (bounds[n_queues] = n).
-void xcd_queues(int n, const int* pocket, const double* cost, int n_queues, int32_t* order,
-                int32_t* bounds);
+// Work queues of a persistent launch: items (ligands) ordered pocket-major, cut into n_queues
+// contiguous ranges of equal total cost; within a range, longest first (pocket_major false) or
+// pocket by pocket, longest first within a pocket (pocket_major true).  order[0..n) receives
+// item indices, bounds[0..n_queues] the range starts (bounds[n_queues] = n).
+void work_queues(int n, const int* pocket, const double* cost, int n_queues, bool pocket_major,
+                 int32_t* order, int32_t* bounds);
 
 }  // namespace exs

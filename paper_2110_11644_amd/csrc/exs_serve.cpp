@@ -122,7 +122,7 @@ struct Request {
 struct Iteration {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    // index upload (pinned host, device): processing order [n], queue bounds [kXcds + 1],
+    // index upload (pinned host, device): processing order [n], queue bounds [kMaxWorkQueues + 1],
     // then per work-list ligand j: arena ligand [n], staging atom offset [n], staging bond offset [n]
     int32_t* d_order = nullptr;
     int32_t* h_order = nullptr;
@@ -310,14 +310,14 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
         Iteration& it = it_[i];
         SRV_TRY(hipStreamCreateWithFlags(&it.stream, hipStreamNonBlocking));
         SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
-        if ((rc = dev_alloc(dev_bufs_, &it.d_order, 4 * (size_t)max_iter_ + kXcds + 1)) ||
-            (rc = dev_alloc(dev_bufs_, &it.d_counter, kXcds)) ||
+        if ((rc = dev_alloc(dev_bufs_, &it.d_order, 4 * (size_t)max_iter_ + kMaxWorkQueues + 1)) ||
+            (rc = dev_alloc(dev_bufs_, &it.d_counter, kMaxWorkQueues)) ||
             (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_rec, (size_t)max_iter_)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_coords, (size_t)3 * EXS_MAX_ATOMS * max_iter_)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_theta, (size_t)EXS_MAX_ROT * max_iter_)))
             return rc;
-        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (4 * (size_t)max_iter_ + kXcds + 1),
+        SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (4 * (size_t)max_iter_ + kMaxWorkQueues + 1),
                               hipHostMallocDefault));
         SRV_TRY(hipHostMalloc((void**)&it.h_res, res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_,
                               hipHostMallocDefault));
@@ -457,15 +457,21 @@ bool Server::launch(Iteration& it) {
         r->scheduled += take;
     }
     if (lig.empty()) return false;
-    // per-XCD queues (pocket-major, equal cost, longest first), then the gather's indices
+    // work queues (queue_plan: spread or pocket-major), then the gather's indices
     const int n = (int)lig.size();
     int32_t* h_ord = it.h_order;
     int32_t* h_bounds = h_ord + n;
-    int32_t* h_lig = h_bounds + kXcds + 1;
+    int32_t* h_lig = h_bounds + kMaxWorkQueues + 1;
     int32_t* h_adst = h_lig + n;
     int32_t* h_rdst = h_adst + n;
     std::vector<int32_t> ord(n);
-    xcd_queues(n, pocket.data(), cost.data(), kXcds, ord.data(), h_bounds);
+    int used = 0;
+    {
+        std::vector<int> seen(pocket_ids_.size(), 0);
+        for (int p : pocket) used += seen[p]++ == 0 ? 1 : 0;
+    }
+    const QueuePlan plan = queue_plan(n, used, wpl_);
+    work_queues(n, pocket.data(), cost.data(), plan.n_queues, plan.pocket_major, ord.data(), h_bounds);
     int atoms = 0, rots = 0;
     for (int j = 0; j < n; ++j) {
         h_ord[j] = lig[ord[j]];
@@ -476,7 +482,7 @@ bool Server::launch(Iteration& it) {
         rots += nrt[j];
     }
     const int32_t* d_bounds = it.d_order + n;
-    const int32_t* d_lig = d_bounds + kXcds + 1;
+    const int32_t* d_lig = d_bounds + kMaxWorkQueues + 1;
     if (up_pending_) (void)hipStreamWaitEvent(it.stream, up_event_, 0);
     DockArgs a = base_;
     a.order = it.d_order;
@@ -484,11 +490,11 @@ bool Server::launch(Iteration& it) {
     a.n_tiles = (a.n_order + lpw_ - 1) / lpw_;
     a.tile_counter = it.d_counter;
     a.queue_bounds = d_bounds;
-    a.n_queues = kXcds;
+    a.n_queues = plan.n_queues;
     a.scratch = it.scratch;
-    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (4 * (size_t)n + kXcds + 1),
+    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (4 * (size_t)n + kMaxWorkQueues + 1),
                                   hipMemcpyHostToDevice, it.stream);
-    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, kXcds, it.stream);
+    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, plan.n_queues, it.stream);
     if (e == hipSuccess)
         e = launch_dock(a, storage_, ppl_, std::min(resident_, a.n_tiles), threads_, lds_, it.stream);
     // results of this work list into staging, then one copy per staging region to pinned memory

@@ -202,6 +202,26 @@ def test_multi_pocket_persistent_and_per_pocket_agree(B, oracle_lib):
     log("mixed stats", stats)
 
 
+def test_pocket_major_persistent_launch_equals_per_pocket(B):
+    """A persistent launch large enough for the pocket-major work queues (each pocket holds
+    more ligands than the device has in flight: 3,072 one-wave ligands at 64 orientations)
+    equals the per-pocket launches bitwise, at one and two ligands per workgroup."""
+    wl = S.Workload("pocketmajor", 92, 7000, 2, (32, 40), 0.375, 8, ("uniform", 10, 24),
+                    ("uniform", 0, 4), S.SearchSettings(64, 8, 1, 27))
+    pockets = [S.make_pocket(wl, i) for i in range(2)]
+    batch = S.make_ligand_batch(wl, 0, wl.n_ligands)
+    per_pocket = np.bincount([batch.ligand(l).pocket for l in range(batch.n_ligands)], minlength=2)
+    log("pocket-major: ligands per pocket", per_pocket.tolist())
+    assert per_pocket.min() >= 3072
+    a = run(B, pockets, batch, wl.search)
+    for lpw in (1, 2):
+        b = run(B, pockets, batch, wl.search, flags=B.EXS_FLAG_PERSISTENT, lpw=lpw)
+        for key in ("score", "best_score", "coords"):
+            assert np.array_equal(a[key], b[key]), (lpw, key)
+        assert np.array_equal(a["desc"]["theta"], b["desc"]["theta"])
+        assert np.array_equal(a["best"]["orient"], b["best"]["orient"])
+
+
 @pytest.mark.parametrize("storage", [0, 1, 2], ids=["f32", "bf16", "f16"])
 def test_odd_unequal_grid_edges(B, oracle_lib, small, storage):
     """A grid with odd, unequal edges (x 45, y 38, z 41 texels) cut from the small pocket, so
