@@ -572,9 +572,9 @@ def main():
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "small", "batched", "precision", "serving", "campaign"])
     ap.add_argument("--tune", action="store_true", help="autotune the tile (batched)")
-    ap.add_argument("--chunk", type=int, default=4096, help="campaign: ligands per request")
+    ap.add_argument("--chunk", type=int, default=16384, help="campaign: ligands per request")
     ap.add_argument("--packers", type=int, default=4, help="campaign: host packing threads")
-    ap.add_argument("--max-iter", type=int, default=4096,
+    ap.add_argument("--max-iter", type=int, default=16384,
                     help="campaign: ligands per server iteration (0 = the server's default)")
     ap.add_argument("--rank-keep", type=int, default=0,
                     help="scale/small: rank each ligand's final poses and keep this many (0 = off)")
