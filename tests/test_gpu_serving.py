@@ -186,3 +186,24 @@ def test_concurrent_submitters_equal_one_batch(B, setup):
     assert np.array_equal(desc["orient"], ref["desc"]["orient"])
     assert np.array_equal(desc["theta"], ref["desc"]["theta"])
     assert np.array_equal(xyz, ref["coords"])
+
+
+def test_large_iterations_with_pocket_major_queues(B, setup):
+    """Iterations large enough for the pocket-major work queues (each pocket of the iteration
+    holds more ligands than the device has in flight: 3,072 one-wave ligands at 64
+    orientations) give, ligand for ligand, the results of one plain launch."""
+    pids, _ = setup
+    ligs = S.make_ligands(WL, 2000, 7000)
+    for i, l in enumerate(ligs):
+        l.pocket = i % 2
+    whole = S.batch_from_ligands(ligs)
+    ref = alone(B, pids, whole)
+    log("serving: one request of 7,000 ligands over 2 pockets, iterations of up to 8,192")
+    res, stats = serve(B, pids, [whole], max_iter_ligands=8192)
+    assert stats["completed"] == 1
+    best, desc, xyz = res[0]["best_score"], res[0]["desc"], res[0]["coords"]
+    assert np.array_equal(best, ref["best_score"])
+    assert np.array_equal(desc["orient"], ref["desc"]["orient"])
+    assert np.array_equal(desc["theta"], ref["desc"]["theta"])
+    assert np.array_equal(desc["tau"], ref["desc"]["tau"])
+    assert np.array_equal(xyz, ref["coords"])
