@@ -577,8 +577,14 @@ void Server::loop() {
             if (admit_locked()) progress = true;
             for (int i = 0; i < n_iters_; ++i) {
                 Iteration& it = it_[i];
-                if (it.running && hipEventQuery(it.done) == hipSuccess) {
+                if (!it.running) continue;
+                const hipError_t q = hipEventQuery(it.done);
+                if (q == hipSuccess) {
                     complete(it);
+                    progress = true;
+                } else if (q != hipErrorNotReady) {   // a device error: fail the server, wake pollers
+                    thread_error_ = hipGetErrorString(q);
+                    it.running = false;
                     progress = true;
                 }
             }
