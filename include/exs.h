@@ -40,7 +40,7 @@ enum { EXS_F32 = 0, EXS_BF16 = 1, EXS_F16 = 2 };
 
 /* ---- search flags -------------------------------------------------------- */
 enum {
-    EXS_FLAG_PERSISTENT = 1, /* one persistent launch pulling ligand tiles from a queue */
+    EXS_FLAG_PERSISTENT = 1, /* one persistent launch pulling ligand tiles from work queues */
     EXS_FLAG_GRAPH = 2       /* capture the job's launches in a hipGraph and replay it   */
 };
 
@@ -340,7 +340,8 @@ int exs_server_poll(int64_t server, int64_t request, int wait, float* best_score
 
 int exs_server_get_stats(int64_t server, exs_server_stats* out);
 
-/* Stop the server: queued requests are dropped, running launches finish. */
+/* Stop the server: requests not yet admitted are dropped; admitted ones are docked to the
+ * end before it returns. */
 int exs_server_destroy(int64_t server);
 
 #ifdef __cplusplus

@@ -11,7 +11,7 @@
 //    its packed data is uploaded on an upload stream;
 //  * iterations: each launch is the persistent dock kernel over a work list of
 //    not-yet-docked ligands of the in-flight requests (oldest request first,
-//    longest ligand first within the list, capped per iteration); up to two
+//    capped per iteration), in the work queues of a persistent launch; up to two
 //    iterations run at once on two streams, so a new iteration fills the CUs
 //    the previous one's tail leaves idle;
 //  * completion: a request whose last ligand finished has its results copied
