@@ -41,8 +41,9 @@ __device__ __forceinline__ uint32_t to16(float v, int storage) {
 // Expand the FP32 master [C][nz][ny][nx] (x fastest) into the per-cell gather layout, one
 // 16-byte entry per thread.  Cells of a channel are indexed (z * cy + y) * cx + x with
 // cx = nx-1, cy = ny-1, cz = nz-1; corner index dx + 2 dy + 4 dz.
-//  FP32 (storage 0): two entries per cell, entry dz = {V(x,y,z+dz), V(x+1,y,z+dz),
-//  V(x,y+1,z+dz), V(x+1,y+1,z+dz)}.
+//  FP32 (storage 0): two entries per cell, entry dz = {V(x,y,z+dz), V(x+1,y,z+dz) - V(x,y,z+dz),
+//  V(x,y+1,z+dz), V(x+1,y+1,z+dz) - V(x,y+1,z+dz)} (x differences rounded in FP32, as the
+//  interpolation's x round would compute them).
 //  16-bit (1 BF16, 2 FP16): one entry per cell, dword j = corner(2j) | corner(2j+1) << 16.
 __global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restrict__ dst,
                                    int nx, int ny, int nz, int64_t per_chan, int64_t count,
@@ -62,8 +63,9 @@ __global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restr
         uint4 o;
         if (storage == 0) {
             const float* q = b + half * nxy;
-            o = make_uint4(__builtin_bit_cast(uint32_t, q[0]), __builtin_bit_cast(uint32_t, q[1]),
-                           __builtin_bit_cast(uint32_t, q[nx]), __builtin_bit_cast(uint32_t, q[nx + 1]));
+            const float d0 = q[1] - q[0], d1 = q[nx + 1] - q[nx];   // x differences, FP32
+            o = make_uint4(__builtin_bit_cast(uint32_t, q[0]), __builtin_bit_cast(uint32_t, d0),
+                           __builtin_bit_cast(uint32_t, q[nx]), __builtin_bit_cast(uint32_t, d1));
         } else {
             uint32_t w[4];
             for (int j = 0; j < 4; ++j) {

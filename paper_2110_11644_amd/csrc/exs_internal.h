@@ -88,7 +88,8 @@ static_assert(sizeof(LigInfo) == 32, "LigInfo layout");
 // One pocket as the kernels see it.
 struct GridDesc {
     const void* tex;       // per-cell gather blocks, one channel every chan_bytes: the 8 corners
-                           // of cell (z*(ny-1)+y)*(nx-1)+x, 32 B in FP32, 16 B in BF16/FP16
+                           // of cell (z*(ny-1)+y)*(nx-1)+x, 32 B in FP32 (x pairs as a, b - a),
+                           // 16 B in BF16/FP16
     const float* master;   // FP32 master texels [C][nz][ny][nx] (FP64 rescoring)
     int nx, ny, nz, channels;
     float ox, oy, oz, inv_h;   // origin and 1/spacing, FP32
