@@ -154,13 +154,15 @@ def test_brute_force_tiny_ligands_on_gpu(B, oracle_lib, small):
 
 def test_degenerate_ligands_and_one_orientation(B, oracle_lib, small):
     """Single-atom and two-atom ligands (no pairs to clash, no rotatable bond), a ligand whose
-    rotatable bond turns one atom, and K = 1 (one restart): full acceptance against the oracle."""
+    rotatable bond turns one atom, a rotatable bond that turns no atom (its far end is
+    terminal), and K = 1 (one restart): full acceptance against the oracle."""
     O = oracle_lib
     p, g, _ = small
     ligs = [Lig([[0.3, -0.2, 0.1]], [2], np.zeros((0, 2), np.int32)),
             Lig([[0, 0, 0], [1.5, 0, 0]], [0, 3], [[0, 1]]),
             Lig([[0, 0, 0], [1.5, 0, 0], [2.0, 1.4, 0], [3.5, 1.4, 0.2]], [1, 2, 3, 0],
-                [[0, 1], [1, 2], [2, 3]], [1])]
+                [[0, 1], [1, 2], [2, 3]], [1]),
+            Lig([[0, 0, 0], [1.5, 0, 0], [2.0, 1.4, 0]], [3, 1, 2], [[0, 1], [1, 2]], [1])]
     batch = S.batch_from_ligands(ligs)
     for s in (S.SearchSettings(8, 8, 1, 27), S.SearchSettings(1, 16, 2, 27), S.SearchSettings(64, 32, 1, 1)):
         log("degenerate ligands, K=%d S=%d P=%d T=%d" % (s.n_orient, s.torsion_steps, s.passes, s.n_offsets))
