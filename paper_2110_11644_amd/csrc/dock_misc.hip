@@ -39,8 +39,10 @@ __device__ __forceinline__ uint32_t to16(float v, int storage) {
 }
 
 // Expand the FP32 master [C][nz][ny][nx] (x fastest) into the per-cell gather layout, one
-// 16-byte entry per thread.  Cells of a channel are indexed (z * cy + y) * cx + x with
-// cx = nx-1, cy = ny-1, cz = nz-1; corner index dx + 2 dy + 4 dz.
+// 16-byte entry per thread; cx = nx-1, cy = ny-1, cz = nz-1 cells, corner index dx + 2 dy + 4 dz.
+// FP32 cells are indexed (z * cy + y) * cx + x; 16-bit cells go in 2 x 2 x 2 bricks (bricks x
+// fastest, cell 4 (z & 1) + 2 (y & 1) + (x & 1) within a brick; cells of an odd edge's padding
+// are zero and never read).
 //  FP32 (storage 0): two entries per cell, entry dz = {V(x,y,z+dz), V(x+1,y,z+dz) - V(x,y,z+dz),
 //  V(x,y+1,z+dz), V(x+1,y+1,z+dz) - V(x,y+1,z+dz)} (x differences rounded in FP32, as the
 //  interpolation's x round would compute them).
@@ -51,14 +53,29 @@ __global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restr
     const int cx = nx - 1, cy = ny - 1;
     const int64_t nxy = (int64_t)nx * ny, chan = nxy * nz;
     const int per_cell = storage == 0 ? 2 : 1;
+    const int cz = nz - 1, bxc = nx / 2, byc = ny / 2;   // 16-bit: bricks per row and per column
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = i / per_chan, e = i - c * per_chan;
         const int64_t cell = e / per_cell;
         const int half = (int)(e - cell * per_cell);
-        const int x = (int)(cell % cx);
-        const int64_t yz = cell / cx;
-        const int y = (int)(yz % cy), z = (int)(yz / cy);
+        int x, y, z;
+        if (storage == 0) {
+            x = (int)(cell % cx);
+            const int64_t yz = cell / cx;
+            y = (int)(yz % cy); z = (int)(yz / cy);
+        } else {
+            const int64_t brick = cell >> 3;
+            const int sub = (int)(cell & 7);
+            x = (int)(brick % bxc) * 2 + (sub & 1);
+            const int64_t rest = brick / bxc;
+            y = (int)(rest % byc) * 2 + ((sub >> 1) & 1);
+            z = (int)(rest / byc) * 2 + (sub >> 2);
+            if (x >= cx || y >= cy || z >= cz) {   // padding of an odd edge: never read
+                dst[i] = make_uint4(0u, 0u, 0u, 0u);
+                continue;
+            }
+        }
         const float* b = src + c * chan + (int64_t)z * nxy + (int64_t)y * nx + x;
         uint4 o;
         if (storage == 0) {
@@ -154,7 +171,8 @@ const void* dock_kernel_fn(int storage, int S, int ppl) {
 }
 
 int64_t expanded_entries(int nx, int ny, int nz, int storage) {
-    return (int64_t)(nx - 1) * (ny - 1) * (nz - 1) * (storage == 0 ? 2 : 1);
+    if (storage == 0) return (int64_t)(nx - 1) * (ny - 1) * (nz - 1) * 2;
+    return (int64_t)8 * (nx / 2) * (ny / 2) * (nz / 2);
 }
 
 hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,

@@ -88,8 +88,8 @@ static_assert(sizeof(LigInfo) == 32, "LigInfo layout");
 // One pocket as the kernels see it.
 struct GridDesc {
     const void* tex;       // per-cell gather blocks, one channel every chan_bytes: the 8 corners
-                           // of cell (z*(ny-1)+y)*(nx-1)+x, 32 B in FP32 (x pairs as a, b - a),
-                           // 16 B in BF16/FP16
+                           // of a cell, 32 B in FP32 (x pairs as a, b - a, cells x fastest),
+                           // 16 B in BF16/FP16 (cells in 2 x 2 x 2 bricks of one line)
     const float* master;   // FP32 master texels [C][nz][ny][nx] (FP64 rescoring)
     int nx, ny, nz, channels;
     float ox, oy, oz, inv_h;   // origin and 1/spacing, FP32
@@ -194,7 +194,8 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
                        size_t lds, hipStream_t st);
 // Per-cell gather layout of a pocket channel, in 16-byte entries: the 8 corners of each of the
-// (nx-1)(ny-1)(nz-1) cells, two entries per cell for FP32, one for 16-bit.
+// (nx-1)(ny-1)(nz-1) cells, two entries per cell for FP32; one per cell for 16-bit, in
+// 2 x 2 x 2 bricks (8 * (nx/2)(ny/2)(nz/2) entries with the padding of odd edges).
 int64_t expanded_entries(int nx, int ny, int nz, int storage);
 hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int nz, int channels,
                               int storage, hipStream_t st);
