@@ -90,6 +90,8 @@ def lib():
         L.orc_rmsd.argtypes = [C.c_int, _dp, _dp]
         L.orc_rank_poses.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double,
                                      C.c_double, _ip, _ip, _ip, _ip]
+        L.orc_decision_margin.argtypes = [C.c_int, _dp, _ip, C.c_int, C.c_double, C.c_double,
+                                          _dp, _ip]
         _lib = L
     return _lib
 
@@ -271,6 +273,21 @@ def unfold_ligand(lig, torsion_steps: int, passes: int, tol: float = 1e-4) -> di
                                    _ptr(b, _ip), nr, _ptr(r, _ip), int(torsion_steps), int(passes),
                                    float(tol), _ptr(X, _dp), _ptr(turns, _ip), C.byref(nt)))
     return dict(xyz=X, turns=turns, near_ties=int(nt.value))
+
+
+def decision_margin(scores: Sequence[float], chosen: int, ambiguous: Optional[Sequence[int]] = None,
+                    near_rel: float = 1e-4, clash_penalty: float = 1.0):
+    """Near-tie bookkeeping of one greedy decision (Sec. 3.1: the search keeps the best
+    candidate): (near_tie, min_gap) for candidate scores with their ambiguous clash-pair
+    counts, `chosen` the kept candidate."""
+    e = np.ascontiguousarray(scores, np.float64)
+    a = None if ambiguous is None else np.ascontiguousarray(ambiguous, np.int32)
+    mg = C.c_double()
+    nt = C.c_int()
+    _check(lib().orc_decision_margin(e.size, _ptr(e, _dp), _ptr(a, _ip), int(chosen),
+                                     float(near_rel), float(clash_penalty), C.byref(mg),
+                                     C.byref(nt)))
+    return bool(nt.value), float(mg.value)
 
 
 def rmsd(a: np.ndarray, b: np.ndarray) -> float:

@@ -478,6 +478,35 @@ int orc_pose_from_desc(const orc_grid *g, const orc_params *prm, int n, const fl
     return ORC_OK;
 }
 
+/* The near-tie bookkeeping of one decision, exposed for tests: candidate scores e[m] with
+ * their ambiguous clash-pair counts amb[m] (NULL = none), chosen candidate c.  *near_tie = 1
+ * when the effective gap to some other candidate is below near_rel * max(|e[c]|, 1);
+ * *min_gap = the smallest effective gap (HUGE_VAL when m = 1). */
+int orc_decision_margin(int m, const double *e, const int *amb, int c, double near_rel,
+                        double clash_penalty, double *min_gap, int *near_tie)
+{
+    if (m < 1 || c < 0 || c >= m || !e) return ORC_EINVAL;
+    orc_energy *cand = (orc_energy *)malloc(sizeof(orc_energy) * (size_t)m);
+    if (!cand) return ORC_ENOMEM;
+    for (int o = 0; o < m; ++o) {
+        cand[o].e = e[o];
+        cand[o].clashes = 0;
+        cand[o].ambiguous = amb ? amb[o] : 0;
+    }
+    orc_params prm;
+    memset(&prm, 0, sizeof(prm));
+    prm.near_rel = near_rel;
+    prm.clash_penalty = clash_penalty;
+    orc_orient_result res;
+    memset(&res, 0, sizeof(res));
+    res.min_gap = HUGE_VAL;
+    decision_margin(cand, m, c, &prm, &res);
+    if (min_gap) *min_gap = res.min_gap;
+    if (near_tie) *near_tie = res.near_tie;
+    free(cand);
+    return ORC_OK;
+}
+
 /* Orientation and moving sets of every rotatable bond (exposed for tests). */
 int orc_rot_topology(int n, int nb, const int *bij, int nrot, const int *rot_bond,
                      int *u, int *v, unsigned char *moving)
