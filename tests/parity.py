@@ -80,10 +80,63 @@ def check_ligand(O, grid, prm, lig, gpu_scores, gpu_desc, best_score, best_desc,
         assert near[kg] or near[kr], "best %.7g (k=%d) vs oracle %.7g (k=%d), no near tie" % (
             g[kg], kg, r[kr], kr)
         stats["best_tie_accepted"] = stats.get("best_tie_accepted", 0) + 1
-    # 4. RMSD of the best pose
+    # 4. RMSD of the best pose (best_xyz None: the caller checks the coordinates itself)
+    if best_xyz is None:
+        return stats
     th, ta = gpu_desc_to_theta_tau(best_desc, nrot)
     X = O.pose_from_desc(grid, prm, lig, kg, th, ta)
     rmsd = float(np.sqrt(np.mean(np.sum((np.asarray(best_xyz, np.float64) - X) ** 2, axis=1))))
     assert rmsd <= RMSD_TOL, "best-pose RMSD %.4g A" % rmsd
     stats["max_rmsd"] = max(stats.get("max_rmsd", 0.0), rmsd)
     return stats
+
+
+def check_best_pose(O, grid, prm, lig, best_score, best_desc, best_xyz, ref=None):
+    """Best pose only (results that carry no per-orientation scores, e.g. served requests):
+    the GPU score is the oracle's FP64 score of the GPU descriptor within tol (+ ambiguous
+    pairs); it equals the oracle's best within tol unless a near tie explains the difference;
+    the coordinates are the descriptor's pose within RMSD_TOL.  Returns the oracle result."""
+    nrot = len(lig.rot)
+    th, ta = gpu_desc_to_theta_tau(best_desc, nrot)
+    k = int(best_desc["orient"])
+    e, _, amb, X = O.rescore_desc(grid, prm, lig, k, th, ta)
+    assert abs(float(best_score) - e) <= tol(e) + prm.clash_penalty * amb, (
+        "best pose: gpu %.7g vs oracle(desc) %.7g (amb %d)" % (best_score, e, amb))
+    if ref is None:
+        ref = O.dock_ligand(grid, prm, lig)
+    kr = int(ref["best_k"])
+    if abs(float(best_score) - ref["best_score"]) > tol(ref["best_score"]):
+        assert ref["near_tie"][k] or ref["near_tie"][kr], (
+            "best %.7g (k=%d) vs oracle %.7g (k=%d), no near tie" % (best_score, k,
+                                                                   ref["best_score"], kr))
+    rmsd = float(np.sqrt(np.mean(np.sum((np.asarray(best_xyz, np.float64) - X) ** 2, axis=1))))
+    assert rmsd <= RMSD_TOL, "best-pose RMSD %.4g A" % rmsd
+    return ref
+
+
+def oracle_topk_fp64_best(O, grid_search, grid_master, prm, lig, top_k, ref=None):
+    """The oracle's own run of the mixed-precision path: its search on the grid the GPU searched
+    (e.g. the RNE-rounded 16-bit grid), its top_k orientations by (score, k), each rescored in
+    FP64 on the FP32 master grid, and the best of those.  Returns (best64, k, ambiguous) where
+    `ambiguous` is set when the selection is not decided beyond the FP32 tolerance: a near tie
+    in a top_k trajectory, top_k-th and next scores within tol, or two rescored scores within
+    tol of the best."""
+    if ref is None:
+        ref = O.dock_ligand(grid_search, prm, lig)
+    sc = ref["score"]
+    K = len(sc)
+    order = sorted(range(K), key=lambda k: (sc[k], k))
+    tk = min(top_k, K)
+    top = order[:tk]
+    e64 = []
+    for k in top:
+        e = O.rescore_desc(grid_master, prm, lig, k, ref["theta"][k], ref["tau"][k])[0]
+        e64.append(e)
+    j = int(np.argmin(e64))
+    amb = bool(any(ref["near_tie"][k] for k in top))
+    if tk < K and abs(sc[order[tk]] - sc[order[tk - 1]]) <= tol(sc[order[tk - 1]]):
+        amb = True
+    srt = sorted(e64)
+    if len(srt) > 1 and srt[1] - srt[0] <= tol(srt[0]):
+        amb = True
+    return float(e64[j]), int(top[j]), amb

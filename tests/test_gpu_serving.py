@@ -207,3 +207,76 @@ def test_large_iterations_with_pocket_major_queues(B, setup):
     assert np.array_equal(desc["theta"], ref["desc"]["theta"])
     assert np.array_equal(desc["tau"], ref["desc"]["tau"])
     assert np.array_equal(xyz, ref["coords"])
+
+
+def test_served_results_match_oracle(B, oracle_lib, setup):
+    """Every ligand of three served requests (FP32 texels) against the FP64 oracle: the served
+    best pose passes the best-pose acceptance (score of its descriptor, best within tolerance
+    or a near tie, coordinates within 0.01 A)."""
+    from parity import check_best_pose
+    O = oracle_lib
+    pids, reqs = setup
+    grids = [O.Grid.of(S.make_pocket(WL, i)) for i in range(3)]
+    prm = O.Params.of(WL.search)
+    res, _ = serve(B, pids, reqs[:3], gap_s=0.002)
+    n = 0
+    for i, r in enumerate(reqs[:3]):
+        for l in range(r.n_ligands):
+            lig = r.ligand(l)
+            a0, a1 = int(r.atom_offset[l]), int(r.atom_offset[l + 1])
+            check_best_pose(O, grids[lig.pocket], prm, lig, res[i]["best_score"][l],
+                            res[i]["desc"][l], res[i]["coords"][a0:a1])
+            n += 1
+    log("served ligands checked against the oracle:", n)
+
+
+def test_served_16bit_topk_matches_oracle(B, oracle_lib):
+    """The mixed-precision served form: BF16 pockets, top-8 FP64 rescoring.  Per ligand of three
+    requests: the served FP64 score is the oracle's FP64 score of the served descriptor on the
+    FP32 master, the coordinates are that pose, and the FP64 best equals the oracle's own run
+    of the same path (search on the rounded grid, its top 8 rescored on the master) within the
+    FP32 tolerance unless that selection is a near tie."""
+    from parity import gpu_desc_to_theta_tau, oracle_topk_fp64_best, tol
+    O = oracle_lib
+    pockets = [S.make_pocket(WL, i) for i in range(3)]
+    pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin, 1) for p in pockets]
+    s = WL.search
+    prm_gpu = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, top_k=8,
+                              ligands_per_wg=1)
+    rng = np.random.default_rng(31)
+    reqs = []
+    for r in range(3):
+        ligs = S.make_ligands(WL, 3000 + 20 * r, int(rng.integers(4, 12)))
+        for l in ligs:
+            l.pocket = r
+        reqs.append(S.batch_from_ligands(ligs))
+    srv = B.exs_server_create(pids, prm_gpu)
+    try:
+        ids = [B.exs_server_submit(srv, r, pocket_ids=pids) for r in reqs]
+        res = [B.exs_server_poll(srv, h, r.n_ligands, int(r.atom_offset[-1]))
+               for h, r in zip(ids, reqs)]
+    finally:
+        B.exs_server_destroy(srv)
+        for pid in pids:
+            B.exs_unload_pocket(pid)
+    g32 = [O.Grid.of(p) for p in pockets]
+    g16 = [O.Grid(S.to_bf16_rne(p.values), p.spacing, p.origin) for p in pockets]
+    prm = O.Params.of(s)
+    n_amb = 0
+    for r, out in zip(reqs, res):
+        for l in range(r.n_ligands):
+            lig = r.ligand(l)
+            d = out["desc"][l]
+            th, ta = gpu_desc_to_theta_tau(d, len(lig.rot))
+            e, _, amb, X = O.rescore_desc(g32[lig.pocket], prm, lig, int(d["orient"]), th, ta)
+            assert abs(float(d["score_fp64"]) - e) <= 1e-9 * max(1.0, abs(e)) + amb
+            assert float(out["best_score"][l]) == np.float32(d["score_fp64"])
+            a0, a1 = int(r.atom_offset[l]), int(r.atom_offset[l + 1])
+            assert np.max(np.abs(out["coords"][a0:a1] - X)) < 1e-5
+            b64, k64, ambiguous = oracle_topk_fp64_best(O, g16[lig.pocket], g32[lig.pocket], prm,
+                                                        lig, 8)
+            if abs(float(d["score_fp64"]) - b64) > tol(b64):
+                assert ambiguous, "ligand %d: served fp64 best %.9g (k=%d) vs oracle %.9g (k=%d)" % (
+                    l, d["score_fp64"], d["orient"], b64, k64)
+                n_amb += 1
+    log("served 16-bit ligands:", sum(r.n_ligands for r in reqs), "accepted on a near tie:", n_amb)
