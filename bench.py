@@ -168,7 +168,7 @@ def gather_probe(B, pid, storage, stream, batch, search, channels, kernel_ms,
 def load_batched_pockets(S, B, storage, stream, log=True, pockets=None):
     wl = S.BATCHED
     if pockets is None:
-        pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+        pockets = S.make_pockets(wl)
     pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin, storage, stream=stream)
             for p in pockets]
     if log:
@@ -273,7 +273,7 @@ def run_precision(args, torch, S, B):
     A = int(batch.atom_offset[-1])
     flags = B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH
     results = {}
-    pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+    pockets = S.make_pockets(wl)
     for name, storage, top_k in (("f32", 0, 0), ("bf16", 1, 8), ("f16", 2, 8)):
         pockets, pids = load_batched_pockets(S, B, storage, stream, log=(name == "f32"),
                                              pockets=pockets)

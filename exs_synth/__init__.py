@@ -221,6 +221,17 @@ def make_pocket(workload: Workload | str, index: int = 0) -> Pocket:
     return Pocket(vals, wl.spacing, org, xyz, w)
 
 
+def make_pockets(workload: Workload | str, indices: Optional[Sequence[int]] = None,
+                 threads: int = 8) -> List[Pocket]:
+    """make_pocket for several indices (default: every pocket of the workload) on a thread
+    pool; the grids are the same as one by one (each pocket draws from its own stream)."""
+    from concurrent.futures import ThreadPoolExecutor
+    wl = WORKLOADS[workload] if isinstance(workload, str) else workload
+    idx = list(range(wl.n_pockets)) if indices is None else list(indices)
+    with ThreadPoolExecutor(max(1, min(threads, len(idx)))) as ex:
+        return list(ex.map(lambda i: make_pocket(wl, i), idx))
+
+
 def pocket_edge(workload: Workload | str, index: int = 0) -> int:
     """Edge of a pocket without building its grid (same draw order as make_pocket)."""
     wl = WORKLOADS[workload] if isinstance(workload, str) else workload

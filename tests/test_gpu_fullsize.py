@@ -79,7 +79,7 @@ def test_scale_workload_full_size(B, oracle_lib):
 def test_batched_workload_full_size(B, oracle_lib):
     O = oracle_lib
     wl, s = S.BATCHED, S.BATCHED.search
-    pockets = [S.make_pocket(wl, i) for i in range(wl.n_pockets)]
+    pockets = S.make_pockets(wl)
     batch = S.make_ligand_batch(wl, 0)
     L, A = batch.n_ligands, int(batch.atom_offset[-1])
     log("batched full size: %d ligands over %d pockets" % (L, len(pockets)))
