@@ -284,6 +284,33 @@ int exs_get_best_poses(int64_t job, int wait, float* best_score, exs_pose_desc* 
  */
 int exs_get_orientation_results(int64_t job, float* score, exs_pose_desc* desc);
 
+/*
+ * Dock an uploaded batch without allocating device memory: for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid allocation).  The
+ * search of exs_dock_batch (same settings, same per-ligand results bit for bit) as one
+ * persistent launch on `stream`, enqueued and not waited for; no job handle.  Its
+ * intermediate buffers (orientation table, work counter, every orientation's score and
+ * descriptor, per-workgroup pose coordinates) live in one static device buffer of
+ * EXS_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs this call on, until
+ * the process ends.  Calls on one device share that buffer: calls that overlap on a device
+ * race, so order them (for example on one stream); the batch and its pockets must stay loaded
+ * until the stream has finished the call's work.
+ *   params       top_k = 0, rank_keep = 0, flags 0 or EXS_FLAG_PERSISTENT (the launch is
+ *                persistent either way); tiles as for exs_dock_batch
+ *   best_score   [L] device, FP32 score of each ligand's best pose
+ *   best_orient  [L] device, its orientation
+ *   best_tau     [L] device, its rigid offsets packed as (uint8)tau_x | tau_y << 8 | tau_z << 16
+ *   best_theta   [R] device, its torsion of each rotatable bond (the batch's bonds, CSR order)
+ *   best_coords  [A*3] device, its coordinates, atom-major x, y, z
+ * Errors: EXS_EINVAL (settings, null outputs, or a batch whose per-orientation results
+ * L * K * 8 + R * K bytes plus one workgroup's pose scratch exceed the buffer: split it),
+ * EXS_ENOENT (unknown batch, unloaded pocket), EXS_EDEVICE.
+ */
+#define EXS_NOALLOC_SCRATCH_BYTES (256u << 20)
+int exs_dock_batch_noalloc(int64_t batch, const exs_search_params* params, void* stream,
+                           float* best_score, int32_t* best_orient, int32_t* best_tau,
+                           uint8_t* best_theta, float* best_coords);
+
 /* Device time of the job's kernels in ms (waits for the job). */
 int exs_job_elapsed_ms(int64_t job, float* ms);
 

@@ -30,7 +30,7 @@ SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_
            "exs_get_ligand_coords", "exs_job_elapsed_ms",
            "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
-           "exs_server_destroy")
+           "exs_server_destroy", "exs_dock_batch_noalloc")
 
 
 class ExsError(RuntimeError):
@@ -95,6 +95,8 @@ def lib():
                                         vp, vp, vp, vp]
         L.exs_dock_batch.argtypes = [i64, C.POINTER(exs_search_params), vp, C.POINTER(i64)]
         L.exs_get_best_poses.argtypes = [i64, C.c_int, vp, vp, vp, vp]
+        L.exs_dock_batch_noalloc.argtypes = [i64, C.POINTER(exs_search_params), vp, vp, vp, vp,
+                                             vp, vp]
         L.exs_get_orientation_results.argtypes = [i64, vp, vp]
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
@@ -229,6 +231,16 @@ def exs_dock_batch(batch_id: int, params: exs_search_params, stream=None) -> int
     out = C.c_int64()
     _check(lib().exs_dock_batch(int(batch_id), C.byref(params), _stream(stream), C.byref(out)))
     return out.value
+
+
+def exs_dock_batch_noalloc(batch_id: int, params: exs_search_params, best_score, best_orient,
+                           best_tau, best_theta, best_coords, stream=None):
+    """Enqueue the search of an uploaded batch without device allocation; results go to the
+    caller's device tensors (float32 [L], int32 [L], int32 [L], uint8 [R], float32 [A, 3])."""
+    ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+    _check(lib().exs_dock_batch_noalloc(int(batch_id), C.byref(params), _stream(stream),
+                                        ptr(best_score), ptr(best_orient), ptr(best_tau),
+                                        ptr(best_theta), ptr(best_coords)))
 
 
 def exs_get_best_poses(job: int, n_ligands: int, n_atoms: int, top_k: int = 0, wait: bool = True,

@@ -23,6 +23,7 @@ SOURCES = [
     ("dock_bf16.hip", True),
     ("dock_f16.hip", True),
     ("dock_misc.hip", True),
+    ("exs_noalloc.hip", True),
     ("exs_api.cpp", False),
     ("exs_serve.cpp", False),
     ("exs_pack.cpp", False),

@@ -219,6 +219,29 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Fibonacci-sphere orientations R_k = Rz(phi_k) Ry(beta_k): z_k = 1 - (2k+1)/K, beta_k = acos z_k,
+// phi_k = k * golden angle, rows of the product in FP64 and rounded to FP32.  Computed on the
+// device so that every launch path (and a path that cannot allocate or copy from the host)
+// reads the same table bit for bit.
+__global__ void orientation_table_kernel(int K, float* __restrict__ r32, double* __restrict__ r64) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+    const double zk = 1.0 - (2.0 * k + 1.0) / (double)K;
+    const double beta = acos(zk), phi = (double)k * golden;
+    const double cb = cos(beta), sb = sin(beta), cp = cos(phi), sp = sin(phi);
+    const double m[9] = {cp * cb, -sp, cp * sb, sp * cb, cp, sp * sb, -sb, 0.0, cb};
+    for (int t = 0; t < 9; ++t) {
+        if (r64) r64[(size_t)k * 9 + t] = m[t];
+        r32[(size_t)k * 9 + t] = (float)m[t];
+    }
+}
+
+hipError_t launch_orientation_table(int K, float* r32, double* r64, hipStream_t st) {
+    hipLaunchKernelGGL(orientation_table_kernel, dim3((K + 63) / 64), dim3(64), 0, st, K, r32, r64);
+    return hipGetLastError();
+}
+
 // Fill the turn tables of the current device: FP32 from the quarter-period literals (the
 // same values the unrolled kernels use), checked against FP64 cos / sin rounded to FP32;
 // FP64 from the host's cos / sin.

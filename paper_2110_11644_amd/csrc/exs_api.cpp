@@ -83,33 +83,19 @@ int ensure_device(int dev) {
     return EXS_OK;
 }
 
-// Fibonacci-sphere orientations R_k = Rz(phi_k) Ry(beta_k): z_k = 1 - (2k+1)/K,
-// beta_k = acos z_k, phi_k = k * golden angle; R_k maps +z to the k-th sphere point.
+// Fibonacci-sphere orientation tables of K orientations, built once per (device, K) by
+// orientation_table_kernel (the no-allocation entry point builds the same table on the device).
 int orientation_tables(int dev, int K, const float** r32, const double** r64) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     DeviceState& d = g_dev[dev];
     auto it = d.orient_tables.find(K);
     if (it == d.orient_tables.end()) {
-        std::vector<double> h64((size_t)K * 9);
-        std::vector<float> h32((size_t)K * 9);
-        const double golden = M_PI * (3.0 - sqrt(5.0));
-        for (int k = 0; k < K; ++k) {
-            double zk = 1.0 - (2.0 * k + 1.0) / (double)K;
-            double beta = acos(zk), phi = (double)k * golden;
-            double cb = cos(beta), sb = sin(beta), cp = cos(phi), sp = sin(phi);
-            // rows of Rz(phi) * Ry(beta)
-            double m[9] = {cp * cb, -sp, cp * sb, sp * cb, cp, sp * sb, -sb, 0.0, cb};
-            for (int t = 0; t < 9; ++t) {
-                h64[(size_t)k * 9 + t] = m[t];
-                h32[(size_t)k * 9 + t] = (float)m[t];
-            }
-        }
         float* d32 = nullptr;
         double* d64 = nullptr;
-        HIP_TRY(hipMalloc(&d32, h32.size() * sizeof(float)));
-        HIP_TRY(hipMalloc(&d64, h64.size() * sizeof(double)));
-        HIP_TRY(hipMemcpy(d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&d32, (size_t)K * 9 * sizeof(float)));
+        HIP_TRY(hipMalloc(&d64, (size_t)K * 9 * sizeof(double)));
+        HIP_TRY(launch_orientation_table(K, d32, d64, nullptr));
+        HIP_TRY(hipStreamSynchronize(nullptr));
         it = d.orient_tables.emplace(K, std::make_pair(d32, d64)).first;
     }
     *r32 = it->second.first;
@@ -154,6 +140,7 @@ struct Batch {
     uint32_t* d_rot_uv = nullptr;
     uint4* d_rot_mask = nullptr;
     GridDesc* d_grids = nullptr;
+    int32_t* d_upload_order = nullptr;   // pocket by pocket, longest first (no-allocation launches)
     std::mutex order_mu;
     std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
     std::map<std::vector<int>, std::vector<int>> group_sizes;
@@ -206,7 +193,7 @@ int dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
 
 void free_batch(Batch* b) {
     void* ptrs[] = {b->d_info, b->d_ref, b->d_ref64, b->d_excl, b->d_rot_uv, b->d_rot_mask,
-                    b->d_grids};
+                    b->d_grids, b->d_upload_order};
     for (void* p : ptrs) if (p) (void)hipFree(p);
     for (auto& kv : b->d_orders) (void)hipFree(kv.second);
     b->d_orders.clear();
@@ -466,9 +453,22 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
             grids[s] = pk[s]->desc;
             b->storage_of_slot.push_back(pk[s]->storage);
         }
+        // one work queue, pocket by pocket and longest first within a pocket, by the cost at the
+        // full search settings (the order of launches that cannot build one of their own)
+        std::vector<int32_t> up_order((size_t)L + kMaxWorkQueues + 1);
+        {
+            std::vector<double> cost(L);
+            std::vector<int> pocket(L);
+            for (int l = 0; l < L; ++l) {
+                cost[l] = ligand_cost(b->info[l].n, b->mcount[l].data(), b->info[l].nrot, 1, 32, 2, 27);
+                pocket[l] = b->info[l].pocket;
+            }
+            work_queues(L, pocket.data(), cost.data(), 1, true, up_order.data(), up_order.data() + L);
+        }
         hipStream_t st = (hipStream_t)stream;
         int rc;
-        if ((rc = dev_upload(&b->d_info, b->info.data(), (size_t)L, st)) ||
+        if ((rc = dev_upload(&b->d_upload_order, up_order.data(), (size_t)L, st)) ||
+            (rc = dev_upload(&b->d_info, b->info.data(), (size_t)L, st)) ||
             (rc = dev_upload(&b->d_ref, ref.data(), (size_t)A, st)) ||
             (rc = dev_upload(&b->d_ref64, ref64.data(), (size_t)A * 3, st)) ||
             (rc = dev_upload(&b->d_excl, excl.data(), (size_t)A, st)) ||
@@ -714,6 +714,94 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
     return hipSuccess;
 }
 
+// Validated search settings of a batch and the launch shape they give.
+struct LaunchShape {
+    int ppl = 1, wpl = 1, lpw = 1, threads = 64, top_k = 0, storage = 0;
+    size_t lds = 0;
+    const void* fn = nullptr;
+};
+
+int launch_shape(const Batch& b, const exs_search_params& p, bool persistent, LaunchShape* out) {
+    if (p.n_orient < 1 || p.n_orient > EXS_MAX_ORIENT)
+        return fail(EXS_EINVAL, "n_orient %d outside [1, %d]", p.n_orient, EXS_MAX_ORIENT);
+    if (p.torsion_steps != 8 && p.torsion_steps != 16 && p.torsion_steps != 32)
+        return fail(EXS_EINVAL, "torsion_steps %d: supported 8, 16, 32", p.torsion_steps);
+    if (p.passes < 0 || p.passes > 64) return fail(EXS_EINVAL, "passes %d outside [0, 64]", p.passes);
+    if (p.n_offsets != 1 && p.n_offsets != 27) return fail(EXS_EINVAL, "n_offsets must be 1 or 27");
+    if (!(p.offset_step_A >= 0.0f) || !(p.clash_cutoff_A >= 0.0f) || !isfinite(p.clash_penalty) ||
+        !isfinite(p.offset_step_A) || !isfinite(p.clash_cutoff_A))
+        return fail(EXS_EINVAL, "offset step, clash cutoff and penalty must be finite, >= 0");
+    if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return fail(EXS_EINVAL, "top_k %d outside [0, %d]", p.top_k, EXS_MAX_TOPK);
+    if (p.n_offsets == 27 && p.passes > 127) return fail(EXS_EINVAL, "too many passes for offsets");
+    if (p.rank_keep < 0 || p.rank_keep > p.n_orient)
+        return fail(EXS_EINVAL, "rank_keep %d outside [0, n_orient]", p.rank_keep);
+    if (p.rank_keep > 0 && (!(p.cluster_rmsd_A >= 0.0f) || !isfinite(p.cluster_rmsd_A)))
+        return fail(EXS_EINVAL, "cluster_rmsd_A must be finite and >= 0");
+    LaunchShape& sh = *out;
+    sh.ppl = p.poses_per_lane ? p.poses_per_lane : 1;
+    if (sh.ppl != 1 && sh.ppl != 2) return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2", sh.ppl);
+    const int K = p.n_orient;
+    sh.wpl = (K + kWave * sh.ppl - 1) / (kWave * sh.ppl);
+    sh.lpw = p.ligands_per_wg;
+    if (sh.lpw == 0) sh.lpw = std::max(1, std::min(kMaxLpw, kMaxWavesPerWg / std::max(1, sh.wpl) / 2));
+    if (sh.lpw != 1 && sh.lpw != 2 && sh.lpw != 4 && sh.lpw != 8)
+        return fail(EXS_EINVAL, "ligands_per_wg %d: supported 1, 2, 4, 8", sh.lpw);
+    sh.threads = sh.lpw * sh.wpl * kWave;
+    if (sh.threads > kMaxThreadsPerWg)
+        return fail(EXS_EINVAL, "workgroup of %d ligands x %d waves exceeds %d threads", sh.lpw, sh.wpl,
+                    kMaxThreadsPerWg);
+    sh.top_k = std::min(p.top_k, K);
+    int storage = -1;
+    for (size_t s = 0; s < b.pockets.size(); ++s) {
+        auto pk = find_pocket(b.pockets[s]);
+        if (!pk) return fail(EXS_ENOENT, "pocket %d of the batch was unloaded", b.pockets[s]);
+        if (storage >= 0 && pk->storage != storage && persistent)
+            return fail(EXS_EINVAL, "persistent launch needs one texel storage for all pockets");
+        storage = storage < 0 ? pk->storage : storage;
+    }
+    sh.storage = storage < 0 ? 0 : storage;
+    sh.lds = dock_lds_bytes(sh.lpw, sh.top_k, sh.lpw * sh.wpl, sh.ppl, p.torsion_steps);
+    if (sh.lds > kMaxLdsBytes)
+        return fail(EXS_EINVAL, "tile of %d ligands x %d waves x %d poses per lane needs %zu B of LDS (max %zu)",
+                    sh.lpw, sh.wpl, sh.ppl, sh.lds, kMaxLdsBytes);
+    sh.fn = dock_kernel_fn(sh.storage, p.torsion_steps, sh.ppl);
+    if (!sh.fn) return fail(EXS_EINVAL, "no kernel for this configuration");
+    if (sh.lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(sh.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+        if (e != hipSuccess) return fail(EXS_EDEVICE, "LDS %zu: %s", sh.lds, hipGetErrorString(e));
+    }
+    return EXS_OK;
+}
+
+// Launch arguments of batch b under settings p (batch, pocket and search fields); outputs,
+// scratch and the processing order are left null.
+void base_args(DockArgs& a, const Batch& b, const exs_search_params& p, const LaunchShape& sh,
+               const float* r32, const double* r64) {
+    memset(&a, 0, sizeof a);
+    a.info = b.d_info; a.ref = b.d_ref; a.ref64 = b.d_ref64; a.excl = b.d_excl;
+    a.rot_uv = b.d_rot_uv; a.rot_mask = b.d_rot_mask; a.grids = b.d_grids;
+    a.rot32 = r32; a.rot64 = r64;
+    a.K = p.n_orient; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
+    a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
+    a.step64 = (double)p.offset_step_A;
+    a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
+    a.pen64 = (double)p.clash_penalty;
+    a.top_k = sh.top_k; a.lpw = sh.lpw; a.wpl = sh.wpl; a.kp = sh.wpl * kWave * sh.ppl;
+    a.rank_keep = p.rank_keep;
+    a.rank_thr2 = p.cluster_rmsd_A * p.cluster_rmsd_A;
+    a.n_max = b.n_max;
+    a.slot_floats = (int64_t)sh.lpw * a.n_max * 3 * a.kp;
+}
+
+// Workgroups of a persistent launch of shape sh that are resident at once on device dev.
+int resident_workgroups(int dev, const LaunchShape& sh) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sh.fn, sh.threads, sh.lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return per_cu * std::max(1, g_dev[dev].cus);
+}
+
 }  // namespace
 
 extern "C" {
@@ -724,43 +812,13 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         auto b = find_batch(batch);
         if (!b) return fail(EXS_ENOENT, "unknown batch %lld", (long long)batch);
         const exs_search_params& p = *params;
-        if (p.n_orient < 1 || p.n_orient > EXS_MAX_ORIENT)
-            return fail(EXS_EINVAL, "n_orient %d outside [1, %d]", p.n_orient, EXS_MAX_ORIENT);
-        if (p.torsion_steps != 8 && p.torsion_steps != 16 && p.torsion_steps != 32)
-            return fail(EXS_EINVAL, "torsion_steps %d: supported 8, 16, 32", p.torsion_steps);
-        if (p.passes < 0 || p.passes > 64) return fail(EXS_EINVAL, "passes %d outside [0, 64]", p.passes);
-        if (p.n_offsets != 1 && p.n_offsets != 27) return fail(EXS_EINVAL, "n_offsets must be 1 or 27");
-        if (!(p.offset_step_A >= 0.0f) || !(p.clash_cutoff_A >= 0.0f) || !isfinite(p.clash_penalty) ||
-            !isfinite(p.offset_step_A) || !isfinite(p.clash_cutoff_A))
-            return fail(EXS_EINVAL, "offset step, clash cutoff and penalty must be finite, >= 0");
-        if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return fail(EXS_EINVAL, "top_k %d outside [0, %d]", p.top_k, EXS_MAX_TOPK);
-        if (p.n_offsets == 27 && p.passes > 127) return fail(EXS_EINVAL, "too many passes for offsets");
-        if (p.rank_keep < 0 || p.rank_keep > p.n_orient)
-            return fail(EXS_EINVAL, "rank_keep %d outside [0, n_orient]", p.rank_keep);
-        if (p.rank_keep > 0 && (!(p.cluster_rmsd_A >= 0.0f) || !isfinite(p.cluster_rmsd_A)))
-            return fail(EXS_EINVAL, "cluster_rmsd_A must be finite and >= 0");
-        int ppl = p.poses_per_lane ? p.poses_per_lane : 1;
-        if (ppl != 1 && ppl != 2) return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2", ppl);
-        const int K = p.n_orient;
-        const int wpl = (K + kWave * ppl - 1) / (kWave * ppl);
-        int lpw = p.ligands_per_wg;
-        if (lpw == 0) lpw = std::max(1, std::min(kMaxLpw, kMaxWavesPerWg / std::max(1, wpl) / 2));
-        if (lpw != 1 && lpw != 2 && lpw != 4 && lpw != 8)
-            return fail(EXS_EINVAL, "ligands_per_wg %d: supported 1, 2, 4, 8", lpw);
-        const int threads = lpw * wpl * kWave;
-        if (threads > kMaxThreadsPerWg)
-            return fail(EXS_EINVAL, "workgroup of %d ligands x %d waves exceeds %d threads", lpw, wpl,
-                        kMaxThreadsPerWg);
-        const int top_k = std::min(p.top_k, K);
         const bool persistent = (p.flags & EXS_FLAG_PERSISTENT) != 0;
-        int storage = -1;
-        for (size_t s = 0; s < b->pockets.size(); ++s) {
-            auto pk = find_pocket(b->pockets[s]);
-            if (!pk) return fail(EXS_ENOENT, "pocket %d of the batch was unloaded", b->pockets[s]);
-            if (storage >= 0 && pk->storage != storage && persistent)
-                return fail(EXS_EINVAL, "persistent launch needs one texel storage for all pockets");
-            storage = storage < 0 ? pk->storage : storage;
-        }
+        LaunchShape sh;
+        if (int rc = launch_shape(*b, p, persistent, &sh)) return rc;
+        const int ppl = sh.ppl, lpw = sh.lpw, threads = sh.threads, top_k = sh.top_k;
+        const int storage = sh.storage;
+        const size_t lds = sh.lds;
+        const int K = p.n_orient;
         int dev;
         if (int rc = current_device(&dev)) return rc;
         if (dev != b->device) return fail(EXS_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
@@ -778,30 +836,12 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         j->device = dev; j->batch = b; j->prm = p; j->stream = st;
         j->L = b->L; j->A = b->A; j->R = b->R; j->K = K; j->top_k = top_k;
         const int L = b->L;
-        const size_t lds = dock_lds_bytes(lpw, top_k, lpw * wpl, ppl, p.torsion_steps);
-        if (lds > kMaxLdsBytes)
-            return fail(EXS_EINVAL, "tile of %d ligands x %d waves x %d poses per lane needs %zu B of LDS (max %zu)",
-                        lpw, wpl, ppl, lds, kMaxLdsBytes);
-        const void* fn = dock_kernel_fn(storage < 0 ? 0 : storage, p.torsion_steps, ppl);
-        if (!fn) return fail(EXS_EINVAL, "no kernel for this configuration");
-        if (lds > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return fail(EXS_EDEVICE, "LDS %zu: %s", lds, hipGetErrorString(e));
-        }
         // workgroup slots of pose scratch: resident workgroups (persistent) or the largest launch
         int64_t slots = 0;
         int resident = 0;
         if (persistent) {
-            int per_cu = 0;
-            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
-            if (e != hipSuccess || per_cu < 1) per_cu = 1;
-            int cus = 0;
-            {
-                std::lock_guard<std::mutex> lk(g_dev_mu);
-                cus = g_dev[dev].cus;
-            }
             const int n_tiles = (L + lpw - 1) / lpw;
-            resident = std::max(1, std::min(n_tiles, per_cu * cus));
+            resident = std::max(1, std::min(n_tiles, resident_workgroups(dev, sh)));
             slots = resident;
         } else {
             for (int gsz : groups) slots = std::max<int64_t>(slots, (gsz + lpw - 1) / lpw);
@@ -829,20 +869,7 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
             j->args = plan->args;
         } else {
             DockArgs& a = j->args;
-            memset(&a, 0, sizeof a);
-            a.info = b->d_info; a.ref = b->d_ref; a.ref64 = b->d_ref64; a.excl = b->d_excl;
-            a.rot_uv = b->d_rot_uv; a.rot_mask = b->d_rot_mask; a.grids = b->d_grids;
-            a.rot32 = r32; a.rot64 = r64;
-            a.K = K; a.S = p.torsion_steps; a.P = p.passes; a.T = p.n_offsets;
-            a.step = p.offset_step_A; a.cut2 = p.clash_cutoff_A * p.clash_cutoff_A; a.pen = p.clash_penalty;
-            a.step64 = (double)p.offset_step_A;
-            a.cut2_64 = (double)p.clash_cutoff_A * (double)p.clash_cutoff_A;
-            a.pen64 = (double)p.clash_penalty;
-            a.top_k = top_k; a.lpw = lpw; a.wpl = wpl; a.kp = wpl * kWave * ppl;
-            a.rank_keep = p.rank_keep;
-            a.rank_thr2 = p.cluster_rmsd_A * p.cluster_rmsd_A;
-            a.n_max = b->n_max;
-            a.slot_floats = (int64_t)lpw * a.n_max * 3 * a.kp;
+            base_args(a, *b, p, sh, r32, r64);
             std::shared_ptr<Plan> fresh;
             if (graph) fresh = std::make_shared<Plan>();
             Alloc al{graph ? &fresh->bufs : &j->bufs, st, !graph};
@@ -1152,3 +1179,41 @@ int exs_release_job(int64_t job) {
 }
 
 }  // extern "C"
+
+namespace exs {
+namespace rt {
+
+int noalloc_plan(int64_t batch, const exs_search_params* params, NoAllocPlan* out) {
+    if (!params || !out) return fail(EXS_EINVAL, "null argument");
+    auto b = find_batch(batch);
+    if (!b) return fail(EXS_ENOENT, "unknown batch %lld", (long long)batch);
+    const exs_search_params& p = *params;
+    if (p.top_k != 0 || p.rank_keep != 0)
+        return fail(EXS_EINVAL, "the no-allocation launch needs top_k = 0 and rank_keep = 0");
+    if (p.flags & ~EXS_FLAG_PERSISTENT)
+        return fail(EXS_EINVAL, "the no-allocation launch takes no flags but EXS_FLAG_PERSISTENT");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    if (dev != b->device) return fail(EXS_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+    LaunchShape sh;
+    if (int rc = launch_shape(*b, p, true, &sh)) return rc;
+    base_args(out->args, *b, p, sh, nullptr, nullptr);
+    DockArgs& a = out->args;
+    a.order = b->d_upload_order;
+    a.n_order = b->L;
+    a.n_tiles = (b->L + sh.lpw - 1) / sh.lpw;
+    a.persistent = 1;
+    a.queue_bounds = nullptr;
+    a.n_queues = 1;
+    out->device = dev;
+    out->storage = sh.storage;
+    out->ppl = sh.ppl;
+    out->threads = sh.threads;
+    out->lds = sh.lds;
+    out->resident = resident_workgroups(dev, sh);
+    out->L = b->L; out->A = b->A; out->R = b->R;
+    return EXS_OK;
+}
+
+}  // namespace rt
+}  // namespace exs

@@ -223,6 +223,8 @@ hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const 
 // Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand.
 hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+// K orientation matrices [K][9] (row-major), FP32 and (unless r64 is null) FP64.
+hipError_t launch_orientation_table(int K, float* r32, double* r64, hipStream_t st);
 hipError_t upload_trig_tables();
 const void* dock_kernel_fn(int storage, int S, int ppl);
 
