@@ -92,6 +92,8 @@ def lib():
                                      C.c_double, _ip, _ip, _ip, _ip]
         L.orc_decision_margin.argtypes = [C.c_int, _dp, _ip, C.c_int, C.c_double, C.c_double,
                                           _dp, _ip]
+        L.orc_rescore2.argtypes = [C.POINTER(_Grid), C.c_int, _dp, _up, C.c_int, _ip, C.c_int, _ip,
+                                   C.c_double, C.c_double, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -345,3 +347,37 @@ def dock_batch(grids: Sequence[Grid], params: Params, batch, threads: Optional[i
         out.update(score=sc.reshape(L, K), near_tie=nt.reshape(L, K).astype(bool), theta=th,
                    tau=ta.reshape(L, K, 3))
     return out
+
+
+# --- fourth step: second-stage rescoring ------------------------------------------------------
+
+RESCORE2_EPS = 0.25     # contact-term well depth of the stand-in score
+RESCORE2_W = 0.5        # threefold torsion-term weight of the stand-in score
+
+
+def rescore2(grid: Grid, lig, X: np.ndarray, sigma: float = 2.0, eps: float = RESCORE2_EPS,
+             w: float = RESCORE2_W):
+    """Sec. 3.1, fourth step: the stand-in chemical score E2 of a pose X [n,3] (grid term +
+    smooth contact term over pairs four or more bonds apart + threefold torsion term of the
+    rotatable bonds; the definition is in exs_oracle.c).  Returns (E2, (grid, contact,
+    torsion))."""
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    t = np.ascontiguousarray(lig.types, dtype=np.uint8)
+    b = np.ascontiguousarray(lig.bonds, dtype=np.int32).reshape(-1)
+    r = np.ascontiguousarray(lig.rot, dtype=np.int32)
+    e = C.c_double()
+    parts = np.zeros(3)
+    _check(lib().orc_rescore2(C.byref(grid.c), Xd.shape[0], _ptr(Xd, _dp), _ptr(t, _up),
+                              b.size // 2, _ptr(b, _ip), r.size, _ptr(r, _ip), float(sigma),
+                              float(eps), float(w), C.byref(e), _ptr(parts, _dp)))
+    return e.value, tuple(parts.tolist())
+
+
+def stage2_best(e2: Sequence[float]) -> int:
+    """Index of the lowest second-stage score in a ranked list (ties: the earlier entry)."""
+    e2 = list(e2)
+    j = 0
+    for i in range(1, len(e2)):
+        if e2[i] < e2[j]:
+            j = i
+    return j

@@ -774,3 +774,87 @@ done:
     free(u); free(v); free(mv); free(Y); free(cand);
     return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Second-stage rescoring of the ranked poses (Sec. 3.1, fourth step)         */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The paper rescores the first 30 poses of each ligand's ranked list with a
+ * richer chemical score (LiGen's), which it does not define.  The stand-in
+ * score of a pose X (FP64, plain definition):
+ *
+ *   E2(X) = sum_i g(X_i, t_i)                                  pocket grid term
+ *         + sum_{i<j, bonddist(i,j) >= 4 or unbonded}
+ *               eps * ((s/d')^12 - 2 (s/d')^6),  d' = max(d_ij, s/2)
+ *                                                              smooth contact term,
+ *                                                              minimum -eps at d = s
+ *         + sum_b w * (1 + cos 3 phi_b)                        threefold torsional strain
+ *
+ * with s the clash cutoff.  phi_b is the dihedral a-i-j-c of rotatable bond b
+ * = (i, j) as listed in the bond list, a the lowest-index neighbour of i other
+ * than j, c the lowest-index neighbour of j other than i; a bond without such a
+ * or c, or whose dihedral is undefined (|(X_i - X_a) x (X_j - X_i)| or
+ * |(X_j - X_i) x (X_c - X_j)| below 1e-9 A^2), contributes nothing.  The dihedral
+ * does not depend on which end is listed first.  parts (may be NULL) receives
+ * the three terms.
+ */
+int orc_rescore2(const orc_grid *g, int n, const double *X, const unsigned char *type, int nb,
+                 const int *bij, int nrot, const int *rot_bond, double sigma, double eps,
+                 double w, double *e2, double parts[3])
+{
+    if (n < 1 || !X || !type || !e2) return ORC_EINVAL;
+    int *dist = (int *)malloc(sizeof(int) * (size_t)n * n);
+    if (!dist) return ORC_ENOMEM;
+    int rc = orc_bond_distances(n, nb, bij, dist);
+    if (rc) { free(dist); return rc; }
+    double grid = 0.0, contact = 0.0, tors = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if ((int)type[i] >= g->channels) { free(dist); return ORC_EINVAL; }
+        grid += orc_grid_value(g, type[i], X + 3 * i);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            int d = dist[(size_t)i * n + j];
+            if (d >= 0 && d <= 3) continue;
+            double dx = X[3 * i] - X[3 * j], dy = X[3 * i + 1] - X[3 * j + 1],
+                   dz = X[3 * i + 2] - X[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r < 0.5 * sigma) r = 0.5 * sigma;
+            double q = sigma / r;
+            double q6 = q * q * q * q * q * q;
+            contact += eps * (q6 * q6 - 2.0 * q6);
+        }
+    for (int b = 0; b < nrot; ++b) {
+        if (rot_bond[b] < 0 || rot_bond[b] >= nb) { free(dist); return ORC_EINVAL; }
+        int i = bij[2 * rot_bond[b]], j = bij[2 * rot_bond[b] + 1];
+        int a = -1, c = -1;
+        for (int k = 0; k < n; ++k) {
+            if (a < 0 && k != j && dist[(size_t)i * n + k] == 1) a = k;
+            if (c < 0 && k != i && dist[(size_t)j * n + k] == 1) c = k;
+        }
+        if (a < 0 || c < 0) continue;
+        double b1[3], b2[3], b3[3];
+        for (int t = 0; t < 3; ++t) {
+            b1[t] = X[3 * i + t] - X[3 * a + t];
+            b2[t] = X[3 * j + t] - X[3 * i + t];
+            b3[t] = X[3 * c + t] - X[3 * j + t];
+        }
+        double n1[3] = {b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2],
+                        b1[0] * b2[1] - b1[1] * b2[0]};
+        double n2[3] = {b2[1] * b3[2] - b2[2] * b3[1], b2[2] * b3[0] - b2[0] * b3[2],
+                        b2[0] * b3[1] - b2[1] * b3[0]};
+        double l1 = sqrt(n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+        double l2 = sqrt(n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+        if (l1 < 1e-9 || l2 < 1e-9) continue;
+        double cph = (n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]) / (l1 * l2);
+        if (cph > 1.0) cph = 1.0;
+        if (cph < -1.0) cph = -1.0;
+        double phi = acos(cph);
+        tors += w * (1.0 + cos(3.0 * phi));
+    }
+    free(dist);
+    *e2 = grid + contact + tors;
+    if (parts) { parts[0] = grid; parts[1] = contact; parts[2] = tors; }
+    return ORC_OK;
+}
