@@ -262,10 +262,20 @@ def distance_sum(X: np.ndarray) -> float:
     return float(lib().orc_distance_sum(X.shape[0], _ptr(X, _dp)))
 
 
-def unfold_ligand(lig, torsion_steps: int, passes: int, tol: float = 1e-4) -> dict:
+UNFOLD_PAIR_TOL = 5e-5   # A per changed distance: the near-tie band of an unfolding decision
+
+
+def unfold_band(n: int, n_moving: int, tol: float = UNFOLD_PAIR_TOL) -> float:
+    """Near-tie band of one unfolding decision: a turn changes the n_moving * (n - n_moving)
+    distances between turning and fixed atoms, each allowed `tol` in another precision."""
+    return tol * n_moving * (n - n_moving)
+
+
+def unfold_ligand(lig, torsion_steps: int, passes: int, tol: float = UNFOLD_PAIR_TOL) -> dict:
     """Sec. 3.1, first step: turn the rotatable bonds (side without atom 0, S turns each, bonds
     in list order, `passes` passes) to maximise the sum of interatomic distances.  Returns
-    xyz [n,3] (FP64, input frame), turns [passes, nrot] and the near-tie count."""
+    xyz [n,3] (FP64, input frame), turns [passes, nrot] and the near-tie count (decisions where
+    another turn's sum is within unfold_band of the kept one)."""
     x, y, z, t, b, r = _lig_arrays(lig)
     n, nr = x.size, r.size
     X = np.zeros((n, 3))

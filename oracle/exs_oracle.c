@@ -731,7 +731,9 @@ double orc_distance_sum(int n, const double *X)
 
 /* Input conformation x, y, z (A), bonds, rotatable bonds.  Out: X_out [n*3] in the input
  * frame (atom 0's side does not move), turns [passes*nrot] (the s kept per pass and bond),
- * *near_ties = decisions where another turn's sum is within tol * max(D, 1) of the kept one. */
+ * *near_ties = decisions where another turn's sum is within tol * m * (n - m) of the kept one,
+ * m the atoms that turn with the bond: a turn changes only the m * (n - m) distances between
+ * turning and fixed atoms, so tol is a per-distance allowance (A) for another precision. */
 int orc_unfold_ligand(int n, const float *x, const float *y, const float *z, int nb,
                       const int *bij, int nrot, const int *rot_bond, int S, int passes,
                       double tol, double *X_out, int *turns, int *near_ties)
@@ -762,9 +764,11 @@ int orc_unfold_ligand(int n, const float *x, const float *y, const float *z, int
             int best = 0;
             for (int s = 1; s < S; ++s)
                 if (cand[s] > cand[best]) best = s;
-            double m = fabs(cand[best]) > 1.0 ? fabs(cand[best]) : 1.0;
+            int nm = 0;
+            for (int i = 0; i < n; ++i) nm += mv[(size_t)b * n + i];
+            double band = tol * (double)nm * (double)(n - nm);
             for (int s = 0; s < S; ++s)
-                if (s != best && cand[best] - cand[s] < tol * m) { ++nt; break; }
+                if (s != best && cand[best] - cand[s] < band) { ++nt; break; }
             if (best != 0)
                 orc_rotate_about_bond(n, X_out, u[b], v[b], mv + (size_t)b * n, 2.0 * ORC_PI * best / S);
             if (turns) turns[p * nrot + b] = best;

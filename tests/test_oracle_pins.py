@@ -627,3 +627,32 @@ def test_unfold_converges_to_a_single_bond_optimum(oracle_lib):
             for s in range(1, S_):
                 Y = O.rotate_about_bond(X, u[b], v[b], moving[b], 2 * np.pi * s / S_)
                 assert O.distance_sum(Y) <= D + 1e-9
+
+
+def test_unfold_near_tie_band_is_per_changed_distance(oracle_lib):
+    """The near-tie band of an unfolding decision is tol * m * (n - m) (m turning atoms): on the
+    all-cis 5-chain the first decision (bond 1-2, m = 2, 6 changed distances) is flagged for a
+    tol just above gap / 6 and not for one just below, where gap is the distance-sum margin of
+    the kept turn over the next best, computed here from the distances themselves."""
+    O = oracle_lib
+    cis = planar_chain(5, cis=True)
+    lig = _Lig(cis, chain_bonds(5), [1])
+    X = cis.astype(np.float32).astype(np.float64)
+    moving = np.array([False, False, False, True, True])
+    axis = X[2] - X[1]
+    axis /= np.linalg.norm(axis)
+    sums = []
+    for s in range(8):
+        a = 2 * np.pi * s / 8
+        Y = X.copy()
+        for i in np.nonzero(moving)[0]:
+            r = X[i] - X[2]
+            Y[i] = X[2] + r * np.cos(a) + np.cross(axis, r) * np.sin(a) + axis * axis.dot(r) * (1 - np.cos(a))
+        D = np.linalg.norm(Y[:, None] - Y[None], axis=-1)
+        sums.append(D[np.triu_indices(5, 1)].sum())
+    srt = sorted(sums, reverse=True)
+    gap = srt[0] - srt[1]
+    assert gap > 1e-3
+    assert O.unfold_ligand(lig, 8, 1, tol=gap / 6 * 1.01)["near_ties"] == 1
+    assert O.unfold_ligand(lig, 8, 1, tol=gap / 6 * 0.99)["near_ties"] == 0
+    assert O.unfold_band(5, 2, 1.0) == 6.0
