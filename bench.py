@@ -35,7 +35,7 @@ def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_counts(binding, batch, search, channels):
+def algorithmic_counts(binding, batch, search, channels, with_c0=False):
     """Per-ligand algorithmic work (one orientation each; multiply by K): texel lookups L,
     pair tests Q and turned atom positions Rot.
       L = n + P * (sum_b (S-1) m_b + (T-1) n),  Q = c0 + P * sum_b x_b,
@@ -45,6 +45,7 @@ def algorithmic_counts(binding, batch, search, channels):
     all S turns is one closed form (the clashing turns form one arc)."""
     S_, P, T = search.torsion_steps, search.passes, search.n_offsets
     L = np.zeros(batch.n_ligands); Q = np.zeros(batch.n_ligands); R = np.zeros(batch.n_ligands)
+    C0 = np.zeros(batch.n_ligands)
     for l in range(batch.n_ligands):
         lig = batch.ligand(l)
         t = binding.exs_pack_topology(lig, channels)
@@ -61,7 +62,9 @@ def algorithmic_counts(binding, batch, search, channels):
             lk += P * (S_ - 1) * m
             q += P * x
             rot += P * (S_ - 1) * m
-        L[l], Q[l], R[l] = lk, q, rot
+        L[l], Q[l], R[l], C0[l] = lk, q, rot, c0
+    if with_c0:
+        return L, Q, R, C0
     return L, Q, R
 
 
@@ -112,22 +115,36 @@ def cpu_baseline(workload, pocket, batch, search, max_ligands=1024, budget_s=20.
 
 
 def roofline_of(B, batch, search, channels, kernel_ms, storage, sample_every=1, traffic=None):
-    """Roofline objects (texel bytes vs HBM peak, FP32 lane-ops vs VALU peak) of one launch over
-    `batch`; the algorithmic counts come from every `sample_every`-th ligand, scaled.
-    `traffic`: measured HBM bytes of the launch, if known."""
+    """Roofline objects of one launch over `batch`: algorithmic texel bytes (8 corners per lookup)
+    against the HBM peak, and FP32 lane-ops against the VALU peak; the counts come from every
+    `sample_every`-th ligand, scaled.  `traffic`: measured HBM bytes of the launch, if known.
+
+    The texel bytes are served from L2 and the last-level cache more than from HBM (measured
+    HBM traffic is about 0.4x of them), so the texel figure is a rate of bytes served by the
+    gather path held against the HBM peak; "dram" gives the HBM side from the counters."""
     idx = list(range(0, batch.n_ligands, sample_every))
     sub = batch if sample_every == 1 else batch.subset(idx)
-    Lk, Qk, Rk = algorithmic_counts(B, sub, search, channels)
+    Lk, Qk, Rk, C0 = algorithmic_counts(B, sub, search, channels, with_c0=True)
     scale = batch.n_ligands / sub.n_ligands
-    K = search.n_orient
+    K, S_ = search.n_orient, search.torsion_steps
     tex_bytes = 8.0 * (4.0 if storage == 0 else 2.0) * K * Lk.sum() * scale
     ops = K * (30.0 * Lk.sum() + 14.0 * Qk.sum() + 6.0 * Rk.sum()) * scale
-    gbs = tex_bytes / (kernel_ms * 1e-3) / 1e9
-    tops = ops / (kernel_ms * 1e-3) / 1e12
-    mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    # the same work with every (moving, static) pair tested at each of the S-1 turns
+    q_turns = C0.sum() + (S_ - 1) * (Qk.sum() - C0.sum())
+    ops_turns = K * (30.0 * Lk.sum() + 7.0 * q_turns + 15.0 * Rk.sum()) * scale
+    sec = kernel_ms * 1e-3
+    gbs = tex_bytes / sec / 1e9
+    tops = ops / sec / 1e12
+    mem = {"bound": "texel-gather", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "ceiling": "MI355X HBM peak (8 TB/s) held against the algorithmic texel bytes, which "
+                      "the gathers take from L2 / last-level cache / HBM"}
+    if traffic:
+        mem["dram"] = {"achieved": round(traffic / sec / 1e9, 3), "unit": "GB/s",
+                       "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)}
     alu = {"bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS,
-           "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": traffic}
+           "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+           "frac_if_every_turn_tested": round(ops_turns / sec / 1e12 / VALU_PEAK_TOPS, 4)}
     roof, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
     roof = dict(roof)
     roof["kernel"] = "exs::dock_kernel"
@@ -564,6 +581,241 @@ def run_campaign(args, torch, S, B):
     print(json.dumps(line), flush=True)
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_batched_20k.npz")
+
+
+def golden_oracle():
+    """FP64 oracle best scores of the first 20,000 batched ligands (written by
+    tests/golden/make_oracle_batched.py, which calls only the oracle), or None."""
+    try:
+        z = np.load(GOLDEN)
+    except OSError:
+        return None
+    return {"best_score": z["best_score"], "near_tie_best": z["near_tie_best"]}
+
+
+def vs_oracle(best, golden):
+    """Top-1 % hit overlap and score error of GPU best scores (ligands 0..) against the oracle's
+    best scores of the declared subset."""
+    ref = golden["best_score"]
+    m = len(ref)
+    got = np.asarray(best[:m], np.float64)
+    hits = top_set(ref, 0.01)
+    err = np.abs(got - ref)
+    rel = err / np.maximum(np.abs(ref), 1.0)
+    return {"subset": m, "hits": len(hits),
+            "top1pct_overlap": round(len(top_set(got, 0.01) & hits) / len(hits), 4),
+            "score_abs_err_max": round(float(err.max()), 6),
+            "score_abs_err_mean": round(float(err.mean()), 6),
+            "score_rel_err_max": round(float(rel.max()), 8),
+            "within_1e-4_rel": round(float(np.mean(rel <= 1e-4)), 4)}
+
+
+def replay(trace, reqs, submit, finish, time_scale=1.0):
+    """Submit each request at its trace arrival time (scaled); a waiter thread finishes them in
+    order.  Returns per-request latency (s), the start time and the completion times."""
+    import threading
+    n = len(trace)
+    lat, done_t, handles = [None] * n, [None] * n, [None] * n
+    ready = [threading.Event() for _ in range(n)]
+    t0 = time.perf_counter()
+
+    def waiter():
+        for i in range(n):
+            ready[i].wait()
+            finish(handles[i], reqs[i])
+            done_t[i] = time.perf_counter()
+            lat[i] = done_t[i] - (t0 + trace[i].arrival_s * time_scale)
+    th = threading.Thread(target=waiter)
+    th.start()
+    for i, r in enumerate(trace):
+        now = time.perf_counter() - t0
+        if r.arrival_s * time_scale > now:
+            time.sleep(r.arrival_s * time_scale - now)
+        handles[i] = submit(reqs[i])
+        ready[i].set()
+    th.join()
+    return np.array(lat), t0, done_t
+
+
+def serve_trace(B, pids, prm, trace, reqs, warm, time_scale=1.0, budget=8 << 30):
+    """The trace through a fresh continuous-batching server: latency percentiles and served
+    docks/s over the requests after the first `warm`."""
+    srv = B.exs_server_create(pids, prm, hbm_budget_bytes=budget)
+    try:
+        lat, t0, done = replay(
+            trace, reqs, lambda b: B.exs_server_submit(srv, b, pocket_ids=pids),
+            lambda h, b: B.exs_server_poll(srv, h, b.n_ligands, int(b.atom_offset[-1])),
+            time_scale)
+        st = B.exs_server_get_stats(srv)
+    finally:
+        B.exs_server_destroy(srv)
+    timed = sum(reqs[i].n_ligands for i in range(warm, len(reqs)))
+    span = done[-1] - (t0 + trace[warm].arrival_s * time_scale)
+    return {"p50_ms": round(float(np.percentile(lat[warm:], 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat[warm:], 99)) * 1e3, 2),
+            "docks_per_s": round(timed / span, 1), "iterations": st["iterations"]}
+
+
+def plain_trace(B, torch, pids, prm, trace, reqs, warm, workers):
+    """The trace with one plain launch per request (upload + dock + fetch), FIFO, served by
+    `workers` host threads each on its own HIP stream (several GPU workers per device)."""
+    import queue
+    import threading
+    q = queue.Queue()
+    events = {}
+
+    def worker():
+        st = torch.cuda.Stream()
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            i, b = item
+            bid = B.exs_upload_ligands(b, pocket_ids=pids, stream=st)
+            job = B.exs_dock_batch(bid, prm, stream=st)
+            B.exs_get_best_poses(job, b.n_ligands, int(b.atom_offset[-1]))
+            B.exs_release_job(job)
+            B.exs_release_ligands(bid)
+            events[i].set()
+    ths = [threading.Thread(target=worker) for _ in range(workers)]
+    for t in ths:
+        t.start()
+    counter = [0]
+
+    def submit(b):
+        i = counter[0]
+        counter[0] += 1
+        events[i] = threading.Event()
+        q.put((i, b))
+        return i
+    try:
+        lat, t0, done = replay(trace, reqs, submit, lambda h, b: events[h].wait())
+    finally:
+        for _ in ths:
+            q.put(None)
+        for t in ths:
+            t.join()
+    timed = sum(reqs[i].n_ligands for i in range(warm, len(reqs)))
+    span = done[-1] - (t0 + trace[warm].arrival_s)
+    return {"workers": workers, "p50_ms": round(float(np.percentile(lat[warm:], 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat[warm:], 99)) * 1e3, 2),
+            "docks_per_s": round(timed / span, 1)}
+
+
+def trace_requests(S, n_req, rate):
+    """Poisson trace of n_req requests and their ligand batches (one pass of the generator)."""
+    trace = S.make_trace(n_req, rate)
+    total = sum(r.size for r in trace)
+    ligs = S.make_ligands(S.SERVING, 0, total)
+    reqs = []
+    for r in trace:
+        part = ligs[r.ligand_start:r.ligand_start + r.size]
+        for l in part:
+            l.pocket = r.pocket
+        reqs.append(S.batch_from_ligands(part))
+    return trace, reqs
+
+
+def batched_launch(B, torch, pids, batch, s, storage, top_k, steps, warmup, stream, flags):
+    """Timed launches of the whole batch: docks/s, mean kernel time (HIP events on the job's
+    stream) and the best-pose output of the last step."""
+    prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                          s.clash_cutoff, s.clash_penalty, top_k=top_k, poses_per_lane=1,
+                          ligands_per_wg=1, flags=flags)
+    bid = B.exs_upload_ligands(batch, pocket_ids=pids, stream=stream)
+    try:
+        dt, kms, out = timed_steps(B, torch, bid, prm, batch.n_ligands,
+                                   int(batch.atom_offset[-1]), steps, warmup, stream, top_k=top_k)
+    finally:
+        B.exs_release_ligands(bid)
+    return batch.n_ligands * steps / dt, kms, dt / steps, out
+
+
+def driver_legs(args, torch, S, B):
+    """The rest of the headline metric, under the same run: the batched workload (100,000
+    ligands over 15 resident pockets) as one persistent launch in a hipGraph, FP32 and with
+    16-bit texels + FP64 top-8 rescoring, beside the plain FP32 one-launch-per-pocket form, with
+    top-1 % hit overlap against the FP64 oracle's best scores of the first 20,000 ligands; and
+    the serving workload (Poisson arrivals at 0.7 x capacity), FP32 and BF16 + top-8, against
+    one plain launch per request from several workers."""
+    wl, s = S.BATCHED, S.BATCHED.search
+    stream = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, args.extra_steps))
+    warm = max(1, min(args.warmup, 2))
+    progress("batched: generating 15 pockets and %d ligands" % wl.n_ligands)
+    pockets = S.make_pockets(wl)
+    batch = S.make_ligand_batch(wl, 0, args.ligands_batched or wl.n_ligands)
+    L = batch.n_ligands
+    golden = golden_oracle()
+    persist = B.EXS_FLAG_PERSISTENT | B.EXS_FLAG_GRAPH
+    out = {"workload": "batched: %d ligands (log-normal atoms, median 35, 10-90; 0-15 rotatable "
+                       "bonds) over 15 resident pockets (edges %s, 8 ch, 0.375 A); K=256, S=32, "
+                       "P=2, T=27" % (L, sorted(set(p.n for p in pockets))),
+           "steps": steps, "warmup": warm,
+           "oracle_subset": None if golden is None else
+           "FP64 oracle best scores of ligands 0..19,999 (tests/golden/oracle_batched_20k.npz)"}
+    legs = {}
+    for name, storage, top_k, flags in (("plain_f32_per_pocket", 0, 0, 0),
+                                        ("persistent_f32", 0, 0, persist),
+                                        ("persistent_f32_top8", 0, 8, persist),
+                                        ("persistent_bf16_top8", 1, 8, persist),
+                                        ("persistent_f16_top8", 2, 8, persist)):
+        pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin, storage, stream=stream)
+                for p in pockets]
+        try:
+            v, kms, step_s, res = batched_launch(B, torch, pids, batch, s, storage, top_k, steps,
+                                                 warm, stream, flags)
+        finally:
+            for pid in pids:
+                B.exs_unload_pocket(pid)
+        best = res["desc"]["score_fp64"] if top_k else res["best_score"]
+        leg = {"docks_per_s": round(v, 1), "ms_per_step": round(step_s * 1e3, 3),
+               "kernel_ms": round(kms, 3), "texels": ("f32", "bf16", "f16")[storage],
+               "top_k_fp64": top_k,
+               "launch": "one launch per pocket" if not flags else "persistent + hipGraph"}
+        if flags:
+            leg["roofline"] = roofline_of(B, batch, s, 8, kms, storage, sample_every=max(1, L // 10000))
+        if golden is not None and L >= len(golden["best_score"]):
+            leg["vs_oracle"] = vs_oracle(best, golden)
+        legs[name] = leg
+        progress("batched %s: %s" % (name, {k: leg[k] for k in ("docks_per_s", "kernel_ms")}))
+    out["legs"] = legs
+    # serving: Poisson arrivals at args.load x the persistent FP32 capacity
+    cap = legs["persistent_f32"]["docks_per_s"]
+    n_req = args.requests + args.requests // 20
+    rate = args.load * cap / 82.0
+    progress("serving: generating %d requests" % n_req)
+    trace, reqs = trace_requests(S, n_req, rate)
+    warm_req = args.requests // 20
+    srv = {"load": args.load, "capacity_docks_per_s": cap, "requests": args.requests,
+           "warmup_requests": warm_req,
+           "ligands": sum(r.n_ligands for r in reqs[warm_req:]),
+           "trace": "Poisson arrivals, 1-512 ligands per request (log-uniform), one of 15 "
+                    "resident pockets each"}
+    for name, storage, top_k in (("served_f32", 0, 0), ("served_bf16_top8", 1, 8)):
+        pids = [B.exs_load_pocket_grid(p.values, p.spacing, p.origin, storage, stream=stream)
+                for p in pockets]
+        try:
+            prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets,
+                                  s.offset_step, s.clash_cutoff, s.clash_penalty, top_k=top_k,
+                                  poses_per_lane=1, ligands_per_wg=1, flags=B.EXS_FLAG_PERSISTENT)
+            srv[name] = serve_trace(B, pids, prm, trace, reqs, warm_req)
+            progress("%s: %s" % (name, srv[name]))
+            if storage == 0:
+                prm_p = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets,
+                                        s.offset_step, s.clash_cutoff, s.clash_penalty,
+                                        poses_per_lane=1, ligands_per_wg=1)
+                srv["plain_per_request_f32"] = plain_trace(B, torch, pids, prm_p, trace, reqs,
+                                                           warm_req, args.plain_workers)
+                progress("plain per request: %s" % srv["plain_per_request_f32"])
+        finally:
+            for pid in pids:
+                B.exs_unload_pocket(pid)
+    out["serving"] = srv
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -581,7 +833,7 @@ def main():
     ap.add_argument("--cluster-rmsd", type=float, default=3.0, help="ranking: RMSD threshold (A)")
     ap.add_argument("--unfold-passes", type=int, default=0,
                     help="scale/small: unfold the ligands first (passes; 0 = off), timed apart")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: timed requests")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: timed requests")
     ap.add_argument("--sweep", default="0.5,0.9", help="serving: other offered loads to serve")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--oracle-sample", type=int, default=192,
@@ -592,6 +844,14 @@ def main():
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="scale: skip the batched / precision / serving legs of the default run")
+    ap.add_argument("--extra-steps", type=int, default=3,
+                    help="timed steps of each batched leg (at most --steps)")
+    ap.add_argument("--ligands-batched", type=int, default=None,
+                    help="ligands of the batched legs (default: the workload's 100,000)")
+    ap.add_argument("--plain-workers", type=int, default=4,
+                    help="host workers (one HIP stream each) of the plain per-request baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -687,6 +947,9 @@ def main():
 
     B.exs_release_ligands(bid)
     B.exs_unload_pocket(pid)
+    extra = None
+    if args.workload == "scale" and not args.no_extra and args.ligands is None:
+        extra = driver_legs(args, torch, S, B)
     line = {
         "metric": "ligand-pocket docks/sec on 1 MI355X",
         "value": round(value, 2),
@@ -718,6 +981,25 @@ def main():
         "host_inclusive": {"upload_ms": round(upload_s * 1e3, 2),
                            "docks_per_s": round(L / (upload_s + dt / args.steps), 2)},
     }
+    if extra is not None:
+        legs = extra["legs"]
+        line["batched"] = extra
+        line["served"] = extra.pop("serving")
+        pick = lambda d, *ks: {k: d[k] for k in ks if k in d}
+        line["target"] = {
+            "plain_f32_per_pocket": dict(pick(legs["plain_f32_per_pocket"], "docks_per_s"),
+                                         **pick(legs["plain_f32_per_pocket"].get("vs_oracle", {}),
+                                                "top1pct_overlap")),
+            **{name: dict(pick(legs[name], "docks_per_s"),
+                          roofline_frac=legs[name]["roofline"]["frac"],
+                          **pick(legs[name].get("vs_oracle", {}), "top1pct_overlap"))
+               for name in ("persistent_f32", "persistent_bf16_top8", "persistent_f16_top8")},
+            "served_f32": pick(line["served"]["served_f32"], "docks_per_s", "p50_ms", "p99_ms"),
+            "served_bf16_top8": pick(line["served"]["served_bf16_top8"], "docks_per_s", "p50_ms",
+                                     "p99_ms"),
+            "plain_per_request_f32": pick(line["served"]["plain_per_request_f32"], "docks_per_s",
+                                          "p50_ms", "p99_ms", "workers"),
+        }
     print(json.dumps(line), flush=True)
 
 

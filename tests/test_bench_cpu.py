@@ -58,8 +58,14 @@ def test_roofline_bound_is_the_larger_fraction(bench, B):
     search = S.SearchSettings(64, 8, 2, 27)
     roof = bench.roofline_of(B, batch, search, 4, kernel_ms=1e-3, storage=0, traffic=123.0)
     fr = {roof["bound"]: roof["frac"], roof["other"]["bound"]: roof["other"]["frac"]}
-    assert set(fr) == {"hbm", "alu"}
+    assert set(fr) == {"texel-gather", "alu"}
     assert roof["frac"] >= roof["other"]["frac"]
     assert roof["traffic"] == 123.0
     # 8 corners x 4 bytes x 64 orientations x 293 lookups in 1 microsecond
-    assert fr["hbm"] == pytest.approx(8 * 4 * 64 * 293 / 1e-6 / 1e9 / 8000.0, rel=1e-3)
+    assert fr["texel-gather"] == pytest.approx(8 * 4 * 64 * 293 / 1e-6 / 1e9 / 8000.0, rel=1e-3)
+    mem = roof if roof["bound"] == "texel-gather" else roof["other"]
+    assert mem["dram"]["achieved"] == pytest.approx(123.0 / 1e-6 / 1e9)
+    # every turn tested: 64 x (30 x 293 + 7 x (1 + 7 x 2) + 15 x 28) lane-ops in 1 microsecond
+    alu = roof if roof["bound"] == "alu" else roof["other"]
+    assert alu["frac_if_every_turn_tested"] == pytest.approx(
+        64 * (30 * 293 + 7 * (1 + 7 * 2) + 15 * 28) / 1e-6 / 1e12 / bench.VALU_PEAK_TOPS, abs=1e-4)
