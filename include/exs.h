@@ -41,7 +41,8 @@ enum { EXS_F32 = 0, EXS_BF16 = 1, EXS_F16 = 2 };
 /* ---- search flags -------------------------------------------------------- */
 enum {
     EXS_FLAG_PERSISTENT = 1, /* one persistent launch pulling ligand tiles from work queues */
-    EXS_FLAG_GRAPH = 2       /* capture the job's launches in a hipGraph and replay it   */
+    EXS_FLAG_GRAPH = 2,      /* capture the job's launches in a hipGraph and replay it   */
+    EXS_FLAG_RESCORE2 = 4    /* rescore the ranked poses with the second-stage score     */
 };
 
 /* ---- limits -------------------------------------------------------------- */
@@ -115,6 +116,29 @@ int exs_get_ligand_coords(int64_t batch, float* xyz);
  * EXS_EINVAL (the job did not rank), EXS_EDEVICE.
  */
 int exs_get_ranked_poses(int64_t job, int wait, int32_t* n_clusters, int32_t* ranked);
+
+/*
+ * Second-stage rescoring of a job run with rank_keep > 0 and EXS_FLAG_RESCORE2 (Sec. 3.1,
+ * fourth step: the first poses of each ligand's ranked list are rescored with a richer score;
+ * the paper's chemical score is not defined there, so the library uses a stand-in), in FP64 on
+ * the device, each pose rebuilt from its descriptor:
+ *   E2(X) = sum_i g(X_i, t_i)                                   grid term on the FP32 master
+ *         + sum over pairs four or more bonds apart (or unbonded) of
+ *           EXS_RESCORE2_CONTACT_EPS * ((s/d')^12 - 2 (s/d')^6), d' = max(d, s/2), s = clash cutoff
+ *         + sum over rotatable bonds of EXS_RESCORE2_TORSION_W * (1 + cos 3 phi), phi the dihedral
+ *           a-u-v-c, a / c the lowest-index neighbours of u / v other than each other (none, or an
+ *           undefined dihedral: no term).
+ * The ligand's final pose is the lowest E2 of its ranked list (ties: the earlier entry).
+ *   score2       [L * rank_keep] E2 of the ranked poses, in ranked order (or NULL)
+ *   best_orient  [L] orientation of the lowest E2 (or NULL)
+ *   best_score2  [L] that E2 (or NULL)
+ * wait = 0 returns EXS_ENOTREADY while the job runs.  Errors: EXS_ENOENT, EXS_EINVAL (the job
+ * was run without the flag), EXS_EDEVICE.
+ */
+#define EXS_RESCORE2_CONTACT_EPS 0.25
+#define EXS_RESCORE2_TORSION_W 0.5
+int exs_get_rescored_poses(int64_t job, int wait, double* score2, int32_t* best_orient,
+                           double* best_score2);
 
 /*
  * Gather probe: the docking kernels' texel lookup (same per-cell blocks, loads and FP32
@@ -334,7 +358,9 @@ int exs_release_job(int64_t job);
  * and several GPU workers per device (Sec. 3.2, 4.3).
  */
 typedef struct {
-    int64_t hbm_budget_bytes;   /* device memory for scratch + the request arena (0: 2 GiB) */
+    int64_t hbm_budget_bytes;   /* device memory for scratch + admitted requests (0: 2 GiB);
+                                   clamped to the free device memory (hipMemGetInfo) less a
+                                   reserve of max(1 GiB, 5 % of the device) at creation */
     int32_t max_iter_ligands;   /* ligands per iteration launch (0: two waves of workgroups)  */
     int32_t max_inflight_iters; /* 1 or 2 (0: 2)                                             */
     int32_t max_arena_ligands;  /* cap on the arena's ligand slots (0: from the budget)       */
@@ -346,6 +372,11 @@ typedef struct {
     int64_t iterations, ligands_docked;
     int64_t arena_ligands, arena_atoms;   /* arena capacity */
     double busy_ms;                       /* summed wall time of iteration launches */
+    int64_t budget_bytes;                 /* HBM budget after the free-memory clamp */
+    int64_t arena_budget_bytes;           /* its part for admitted requests */
+    int64_t admitted_bytes;               /* bytes of the requests admitted now */
+    int64_t peak_admitted_bytes;          /* the most ever admitted at once */
+    int64_t peak_queued;                  /* the most requests ever waiting for admission */
 } exs_server_stats;
 
 /* Start a server on the current device for the given pockets (same texel
@@ -354,8 +385,10 @@ typedef struct {
 int exs_server_create(const int32_t* pocket_ids, int n_pockets, const exs_search_params* params,
                       const exs_server_config* cfg, int64_t* server_out);
 
-/* Queue one request (host arrays, copied).  EXS_ENOMEM if it can never fit in
- * the arena.  request_out receives its handle. */
+/* Queue one request (host arrays, copied).  It is admitted when its device bytes
+ * (L * (76 + 12 K + 28 top_k) + 68 A + R * (21 + K + top_k)) fit in the arena budget beside
+ * the requests admitted before it (FIFO).  EXS_ENOMEM if it can never fit.  request_out
+ * receives its handle. */
 int exs_server_submit(int64_t server, const exs_ligand_batch* request, int64_t* request_out);
 
 /* Results of a request: best_score [L], desc [L], coords [A*3] (any may be
@@ -370,6 +403,42 @@ int exs_server_get_stats(int64_t server, exs_server_stats* out);
 /* Stop the server: requests not yet admitted are dropped; admitted ones are docked to the
  * end before it returns. */
 int exs_server_destroy(int64_t server);
+
+/* ---- campaign: a library screened on one device ---------------------------
+ *
+ * The paper's docking application is a pipeline of a reader, a splitter, docking workers and a
+ * writer joined by queues, which keeps the GPUs fed while the host prepares ligands (Sec. 3.2,
+ * several workers per GPU in Sec. 4.3).  exs_campaign_run does that on one device for a library
+ * in host memory: it validates every ligand and computes its search cost on `packers` host
+ * threads, cuts the library, most costly ligands first, into chunks of chunk_ligands, and
+ * streams the chunks through a server (exs_server_*) configured by `server`: packer threads
+ * pack and submit chunks while earlier ones dock.  It returns when every ligand is docked.
+ */
+typedef struct {
+    int32_t chunk_ligands;      /* ligands per chunk (0: 16384)                              */
+    int32_t packers;            /* host threads that validate, pack and submit (0: 4)       */
+    double hit_fraction;        /* hits kept: the best round(L * hit_fraction), at least 1
+                                   (0: 0.01, the top 1 %)                                    */
+    exs_server_config server;   /* the serving engine the chunks go through                 */
+} exs_campaign_config;
+
+typedef struct {
+    int64_t ligands, chunks, iterations;
+    int32_t hits, pad;
+    double seconds;             /* wall time of the call */
+} exs_campaign_stats;
+
+/* Screen `library` (host CSR batch; pocket_id = handles among pocket_ids, all of one texel
+ * storage) with `params` (top_k allowed: the best score is then the FP64 one; rank_keep must be
+ * 0).  Outputs: best_score [L] (host, or NULL) each ligand's best score, by library index; hits
+ * [round(L * hit_fraction)] (host, or NULL) the library indices of the best ligands, best first
+ * (ties to the lower index, NaN last); *n_hits_out their count; stats (or NULL).  All-or-nothing
+ * validation: an invalid ligand gives EXS_EINVAL naming it before any docking.  Errors:
+ * EXS_EINVAL, EXS_ENOMEM (the server's budget, or a chunk larger than its arena), EXS_EDEVICE. */
+int exs_campaign_run(const int32_t* pocket_ids, int n_pockets, const exs_search_params* params,
+                     const exs_ligand_batch* library, const exs_campaign_config* cfg,
+                     float* best_score, int32_t* hits, int32_t* n_hits_out,
+                     exs_campaign_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -16,19 +16,16 @@ import numpy as np
 
 from . import binding as B
 
-PPL_CHOICES = (1, 2)
+PPL_CHOICES = (1, 2, 4)
 LPW_CHOICES = (1, 2, 4, 8)
-MAX_THREADS = 512
 
 
 def candidate_tiles(n_orient: int) -> List[Tuple[int, int]]:
-    out = []
-    for ppl in PPL_CHOICES:
-        wpl = -(-n_orient // (64 * ppl))
-        for lpw in LPW_CHOICES:
-            if lpw * wpl * 64 <= MAX_THREADS:
-                out.append((ppl, lpw))
-    return out
+    """Every (poses per lane, ligands per workgroup) of {1, 2, 4} x {1, 2, 4, 8}: the library
+    fits any of them in a workgroup (its waves take a tile's orientation chunks in turn when
+    the tile has more chunks than the workgroup has waves) and refuses one only when a single
+    wave's LDS does not fit, which tune() then skips."""
+    return [(ppl, lpw) for ppl in PPL_CHOICES for lpw in LPW_CHOICES]
 
 
 def cache_path() -> str:

@@ -14,11 +14,14 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libexs.so")
+# the in-tree build; EXS_LIBRARY names another build of the same sources (e.g. one compiled with
+# other tuning constants) to load instead
+LIB_PATH = os.environ.get("EXS_LIBRARY") or os.path.join(_HERE, "libexs.so")
 
 EXS_OK, EXS_EINVAL, EXS_ENOMEM, EXS_EDEVICE, EXS_ENOTREADY, EXS_ENOENT = 0, -1, -2, -3, -4, -5
 EXS_F32, EXS_BF16, EXS_F16 = 0, 1, 2
-EXS_FLAG_PERSISTENT, EXS_FLAG_GRAPH = 1, 2
+EXS_FLAG_PERSISTENT, EXS_FLAG_GRAPH, EXS_FLAG_RESCORE2 = 1, 2, 4
+EXS_RESCORE2_CONTACT_EPS, EXS_RESCORE2_TORSION_W = 0.25, 0.5
 EXS_MAX_ATOMS, EXS_MAX_ROT, EXS_MAX_CHANNELS, EXS_MAX_ORIENT, EXS_MAX_TOPK = 128, 32, 16, 1024, 32
 
 STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
@@ -30,7 +33,8 @@ SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_
            "exs_get_ligand_coords", "exs_job_elapsed_ms",
            "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
-           "exs_server_destroy", "exs_dock_batch_noalloc")
+           "exs_server_destroy", "exs_dock_batch_noalloc", "exs_get_rescored_poses",
+           "exs_campaign_run")
 
 
 class ExsError(RuntimeError):
@@ -64,7 +68,20 @@ class exs_server_config(C.Structure):
 class exs_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64),
                 ("inflight", C.c_int64), ("iterations", C.c_int64), ("ligands_docked", C.c_int64),
-                ("arena_ligands", C.c_int64), ("arena_atoms", C.c_int64), ("busy_ms", C.c_double)]
+                ("arena_ligands", C.c_int64), ("arena_atoms", C.c_int64), ("busy_ms", C.c_double),
+                ("budget_bytes", C.c_int64), ("arena_budget_bytes", C.c_int64),
+                ("admitted_bytes", C.c_int64), ("peak_admitted_bytes", C.c_int64),
+                ("peak_queued", C.c_int64)]
+
+
+class exs_campaign_config(C.Structure):
+    _fields_ = [("chunk_ligands", C.c_int32), ("packers", C.c_int32), ("hit_fraction", C.c_double),
+                ("server", exs_server_config)]
+
+
+class exs_campaign_stats(C.Structure):
+    _fields_ = [("ligands", C.c_int64), ("chunks", C.c_int64), ("iterations", C.c_int64),
+                ("hits", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double)]
 
 
 # numpy view of exs_pose_desc (56 bytes, natural alignment)
@@ -101,6 +118,7 @@ def lib():
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
         L.exs_get_ranked_poses.argtypes = [i64, C.c_int, vp, vp]
+        L.exs_get_rescored_poses.argtypes = [i64, C.c_int, vp, vp, vp]
         L.exs_unfold_ligands.argtypes = [i64, C.c_int, C.c_int, vp, vp]
         L.exs_get_ligand_coords.argtypes = [i64, vp]
         L.exs_gather_probe.argtypes = [i32, i64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_uint32, vp,
@@ -111,6 +129,9 @@ def lib():
         L.exs_server_poll.argtypes = [i64, i64, C.c_int, vp, vp, vp, C.POINTER(C.c_double)]
         L.exs_server_get_stats.argtypes = [i64, C.POINTER(exs_server_stats)]
         L.exs_server_destroy.argtypes = [i64]
+        L.exs_campaign_run.argtypes = [vp, C.c_int, C.POINTER(exs_search_params),
+                                       C.POINTER(exs_ligand_batch), C.POINTER(exs_campaign_config),
+                                       vp, vp, C.POINTER(C.c_int32), C.POINTER(exs_campaign_stats)]
         for name in SYMBOLS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.exs_version.restype = C.c_char_p
@@ -286,6 +307,16 @@ def exs_get_ranked_poses(job: int, n_ligands: int, rank_keep: int, wait: bool = 
     return nc, rk
 
 
+def exs_get_rescored_poses(job: int, n_ligands: int, rank_keep: int, wait: bool = True) -> dict:
+    """Second-stage scores [L, rank_keep] of the ranked poses, and per ligand the orientation
+    and score of the lowest, of a job run with rank_keep > 0 and EXS_FLAG_RESCORE2."""
+    sc = np.zeros((n_ligands, rank_keep), np.float64)
+    bk = np.zeros(n_ligands, np.int32)
+    bs = np.zeros(n_ligands, np.float64)
+    _check(lib().exs_get_rescored_poses(int(job), 1 if wait else 0, _p(sc), _p(bk), _p(bs)))
+    return dict(score2=sc, best_orient=bk, best_score2=bs)
+
+
 def exs_job_elapsed_ms(job: int) -> float:
     ms = C.c_float()
     _check(lib().exs_job_elapsed_ms(int(job), C.byref(ms)))
@@ -348,3 +379,26 @@ def exs_server_get_stats(server: int) -> dict:
 
 def exs_server_destroy(server: int):
     _check(lib().exs_server_destroy(int(server)))
+
+
+def exs_campaign_run(pocket_ids, params: exs_search_params, library, chunk_ligands: int = 0,
+                     packers: int = 0, hit_fraction: float = 0.0, hbm_budget_bytes: int = 0,
+                     max_iter_ligands: int = 0, max_inflight_iters: int = 0,
+                     max_arena_ligands: int = 0, library_pocket_ids=None) -> dict:
+    """Screen a host CSR library (pocket_id: handles, or indices into library_pocket_ids).
+    Returns best_score [L], hits (library indices, best first) and the campaign stats."""
+    pk = np.ascontiguousarray(pocket_ids, dtype=np.int32)
+    s, keep = _batch_struct(library, library_pocket_ids)
+    L = int(s.n_ligands)
+    n_hits_max = max(1, int(round(L * (hit_fraction if hit_fraction > 0 else 0.01))))
+    best = np.zeros(L, np.float32)
+    hits = np.zeros(n_hits_max + 1, np.int32)
+    nh = C.c_int32()
+    st = exs_campaign_stats()
+    cfg = exs_campaign_config(int(chunk_ligands), int(packers), float(hit_fraction),
+                              exs_server_config(int(hbm_budget_bytes), int(max_iter_ligands),
+                                                int(max_inflight_iters), int(max_arena_ligands), 0))
+    _check(lib().exs_campaign_run(_p(pk), int(pk.size), C.byref(params), C.byref(s), C.byref(cfg),
+                                  _p(best), _p(hits), C.byref(nh), C.byref(st)))
+    return dict(best_score=best, hits=hits[:nh.value].copy(),
+                stats={name: getattr(st, name) for name, _ in exs_campaign_stats._fields_})

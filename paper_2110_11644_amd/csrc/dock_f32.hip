@@ -11,7 +11,8 @@ hipError_t launch_dock_f32(const DockArgs& a, int ppl, dim3 grid, dim3 block, si
         hipLaunchKernelGGL((dock_kernel<SS, PP, TexF32>), grid, block, lds, st, a); \
         return hipGetLastError(); \
     }
-    EXS_LAUNCH(8, 1) EXS_LAUNCH(8, 2) EXS_LAUNCH(16, 1) EXS_LAUNCH(16, 2) EXS_LAUNCH(32, 1) EXS_LAUNCH(32, 2)
+    EXS_LAUNCH(8, 1) EXS_LAUNCH(8, 2) EXS_LAUNCH(8, 4) EXS_LAUNCH(16, 1) EXS_LAUNCH(16, 2)
+    EXS_LAUNCH(16, 4) EXS_LAUNCH(32, 1) EXS_LAUNCH(32, 2) EXS_LAUNCH(32, 4)
 #undef EXS_LAUNCH
     return hipErrorInvalidValue;
 }
@@ -19,7 +20,8 @@ hipError_t launch_dock_f32(const DockArgs& a, int ppl, dim3 grid, dim3 block, si
 const void* dock_kernel_fn_f32(int S, int ppl) {
 #define EXS_FN(SS, PP) \
     if (S == SS && ppl == PP) return reinterpret_cast<const void*>(&dock_kernel<SS, PP, TexF32>);
-    EXS_FN(8, 1) EXS_FN(8, 2) EXS_FN(16, 1) EXS_FN(16, 2) EXS_FN(32, 1) EXS_FN(32, 2)
+    EXS_FN(8, 1) EXS_FN(8, 2) EXS_FN(8, 4) EXS_FN(16, 1) EXS_FN(16, 2) EXS_FN(16, 4)
+    EXS_FN(32, 1) EXS_FN(32, 2) EXS_FN(32, 4)
 #undef EXS_FN
     return nullptr;
 }

@@ -6,6 +6,7 @@
 
 #include "exs_internal.h"
 #include "rank_poses.inc"
+#include "rescore2.inc"
 #include "unfold.inc"
 
 namespace exs {
@@ -197,6 +198,15 @@ hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_rescore2(const DockArgs& a, int n_lig, hipStream_t st) {
+    if (n_lig <= 0) return hipSuccess;
+    constexpr int kWavesPerBlock = 4;
+    const size_t per_wave = sizeof(LigLds) + (size_t)kMaxAtoms * 3 * sizeof(double);
+    hipLaunchKernelGGL(rescore2_kernel, dim3((n_lig + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(kWavesPerBlock * kWave), kWavesPerBlock * per_wave, st, a, n_lig);
+    return hipGetLastError();
+}
+
 hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
                          const uint4* rot_mask, int32_t* turns, int n_lig, int R, int S, int passes,
                          hipStream_t st) {
@@ -211,6 +221,29 @@ hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const 
         case 32: hipLaunchKernelGGL(unfold_kernel<32>, grid, block, lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// flag |= 1 for a non-finite texel, |= 2 for a finite texel that rounds to infinity in the
+// 16-bit storage (RNE thresholds: FP16 |v| >= 65520, BF16 |v| >= 0x7f7f8000).
+__global__ void check_texels_kernel(const float* __restrict__ v, int64_t count, int storage,
+                                    int* flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = __builtin_bit_cast(uint32_t, v[i]) & 0x7fffffffu;
+        if (a >= 0x7f800000u) bad |= 1;
+        else if ((storage == 2 && a >= 0x477ff000u) || (storage == 1 && a >= 0x7f7f8000u)) bad |= 2;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+hipError_t launch_check_texels(const float* v, int64_t count, int storage, int* flag, hipStream_t st) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(check_texels_kernel, dim3((unsigned)blocks), dim3(256), 0, st, v, count,
+                       storage, flag);
     return hipGetLastError();
 }
 
@@ -267,7 +300,8 @@ hipError_t upload_trig_tables() {
     double t64[kTrigEntries];
     if (!fill_trig<8>(t32, t64) || !fill_trig<16>(t32, t64) || !fill_trig<32>(t32, t64))
         return hipErrorInvalidValue;   // a literal of the quarter-period table is wrong
-    hipError_t e = upload_trig_f32(t32, t64);
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_trig64), t64, sizeof(double) * kTrigEntries);
+    if (e == hipSuccess) e = upload_trig_f32(t32, t64);
     if (e == hipSuccess) e = upload_trig_bf16(t32, t64);
     if (e == hipSuccess) e = upload_trig_f16(t32, t64);
     return e;

@@ -103,6 +103,16 @@ int orientation_tables(int dev, int K, const float** r32, const double** r64) {
     return EXS_OK;
 }
 
+// A finite FP32 texel that rounds (to nearest even) to infinity in 16-bit storage: FP16 from
+// 65520 (halfway between 65504 and 65536, a tie that rounds to the even 65536 = inf), BF16
+// from 0x7f7f8000 (halfway past the largest finite BF16, likewise).
+bool overflows_storage(float v, int storage) {
+    const uint32_t a = __builtin_bit_cast(uint32_t, v) & 0x7fffffffu;
+    if (storage == EXS_F16) return a >= __builtin_bit_cast(uint32_t, 65520.0f);
+    if (storage == EXS_BF16) return a >= 0x7f7f8000u;
+    return false;
+}
+
 // ---- registries --------------------------------------------------------------------------------
 
 struct Pocket {
@@ -141,6 +151,7 @@ struct Batch {
     uint4* d_rot_mask = nullptr;
     GridDesc* d_grids = nullptr;
     int32_t* d_upload_order = nullptr;   // pocket by pocket, longest first (no-allocation launches)
+    uint32_t* d_rot_ac = nullptr;        // [R] dihedral neighbours a | c << 16 of each rotatable bond
     std::mutex order_mu;
     std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
     std::map<std::vector<int>, std::vector<int>> group_sizes;
@@ -193,7 +204,7 @@ int dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
 
 void free_batch(Batch* b) {
     void* ptrs[] = {b->d_info, b->d_ref, b->d_ref64, b->d_excl, b->d_rot_uv, b->d_rot_mask,
-                    b->d_grids, b->d_upload_order};
+                    b->d_grids, b->d_upload_order, b->d_rot_ac};
     for (void* p : ptrs) if (p) (void)hipFree(p);
     for (auto& kv : b->d_orders) (void)hipFree(kv.second);
     b->d_orders.clear();
@@ -272,8 +283,12 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
             return fail(EXS_EINVAL, "a grid channel must expand to < 2 GiB (32 B per FP32 cell, 16 B per 16-bit cell)");
         const int64_t count = chan * channels;
         if (!values_on_device) {
-            for (int64_t i = 0; i < count; ++i)
+            for (int64_t i = 0; i < count; ++i) {
                 if (!isfinite(values[i])) return fail(EXS_EINVAL, "texel %lld is not finite", (long long)i);
+                if (overflows_storage(values[i], storage))
+                    return fail(EXS_EINVAL, "texel %lld (%g) overflows %s storage", (long long)i,
+                                (double)values[i], storage == EXS_F16 ? "FP16" : "BF16");
+            }
         }
         int dev;
         if (int rc = current_device(&dev)) return rc;
@@ -296,6 +311,20 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         HIP_TRY(hipMemcpyAsync(p->master, values, (size_t)count * sizeof(float),
                                values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
         HIP_TRY(hipMalloc(&p->tex, (size_t)tex_chan_bytes * channels));
+        if (values_on_device) {   // the same checks on the device copy
+            int* flag = nullptr;
+            HIP_TRY(hipMallocAsync(&flag, sizeof(int), st));
+            int bad = 0;
+            hipError_t e = launch_zero_ints(flag, 1, st);
+            if (e == hipSuccess) e = launch_check_texels(p->master, count, storage, flag, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            (void)hipFreeAsync(flag, st);
+            if (e != hipSuccess) return fail(EXS_EDEVICE, "texel check: %s", hipGetErrorString(e));
+            if (bad & 1) return fail(EXS_EINVAL, "a texel is not finite");
+            if (bad & 2)
+                return fail(EXS_EINVAL, "a texel overflows %s storage", storage == EXS_F16 ? "FP16" : "BF16");
+        }
         HIP_TRY(launch_expand_grid(p->master, p->tex, nx, ny, nz, channels, storage, st));
         HIP_TRY(hipStreamSynchronize(st));
         GridDesc& g = p->desc;
@@ -416,7 +445,7 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
         std::vector<float4> ref(A);
         std::vector<double> ref64((size_t)A * 3);
         std::vector<uint4> excl(A);
-        std::vector<uint32_t> ruv(R);
+        std::vector<uint32_t> ruv(R), rot_ac(R);
         std::vector<uint4> rmask(R);
         b->info.resize(L);
         b->mcount.resize(L);
@@ -442,7 +471,20 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
                 excl[a0 + i] = p.excl[i].as_uint4();
             }
             b->mcount[l].resize(p.nrot);
+            const int b0 = in->bond_offset[l], nbl = in->bond_offset[l + 1] - b0;
             for (int r = 0; r < p.nrot; ++r) {
+                // lowest-index neighbours of u (other than v) and of v (other than u): the
+                // dihedral of the bond in the second-stage score
+                const int u = p.rot_u[r], v = p.rot_v[r];
+                int na = 0xffff, nc = 0xffff;
+                for (int e = 0; e < nbl; ++e) {
+                    const int bi = in->bond_ij[2 * (size_t)(b0 + e)], bj = in->bond_ij[2 * (size_t)(b0 + e) + 1];
+                    if (bi == u && bj != v) na = std::min(na, bj);
+                    if (bj == u && bi != v) na = std::min(na, bi);
+                    if (bi == v && bj != u) nc = std::min(nc, bj);
+                    if (bj == v && bi != u) nc = std::min(nc, bi);
+                }
+                rot_ac[r0 + r] = (uint32_t)na | ((uint32_t)nc << 16);
                 ruv[r0 + r] = (uint32_t)p.rot_u[r] | ((uint32_t)p.rot_v[r] << 16);
                 rmask[r0 + r] = p.moving[r].as_uint4();
                 b->mcount[l][r] = (int16_t)p.moving[r].count();
@@ -473,6 +515,7 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
             (rc = dev_upload(&b->d_ref64, ref64.data(), (size_t)A * 3, st)) ||
             (rc = dev_upload(&b->d_excl, excl.data(), (size_t)A, st)) ||
             (rc = dev_upload(&b->d_rot_uv, ruv.data(), (size_t)R, st)) ||
+            (rc = dev_upload(&b->d_rot_ac, rot_ac.data(), (size_t)R, st)) ||
             (rc = dev_upload(&b->d_rot_mask, rmask.data(), (size_t)R, st)) ||
             (rc = dev_upload(&b->d_grids, grids.data(), grids.size(), st))) {
             free_batch(b.get());
@@ -695,6 +738,7 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         if (e != hipSuccess) return e;
         e = launch_dock(a, storage, ppl, resident, threads, lds, st);
         if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, st);
+        if (e == hipSuccess && a.rescore2) e = launch_rescore2(a, b.L, st);
         return e;
     }
     int start = 0;
@@ -710,8 +754,10 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         if (e != hipSuccess) return e;
         start += gsz;
     }
-    if (base.rank_keep > 0) return launch_rank(base, b.L, st);
-    return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (base.rank_keep > 0) e = launch_rank(base, b.L, st);
+    if (e == hipSuccess && base.rescore2) e = launch_rescore2(base, b.L, st);
+    return e;
 }
 
 // Validated search settings of a batch and the launch shape they give.
@@ -737,20 +783,24 @@ int launch_shape(const Batch& b, const exs_search_params& p, bool persistent, La
         return fail(EXS_EINVAL, "rank_keep %d outside [0, n_orient]", p.rank_keep);
     if (p.rank_keep > 0 && (!(p.cluster_rmsd_A >= 0.0f) || !isfinite(p.cluster_rmsd_A)))
         return fail(EXS_EINVAL, "cluster_rmsd_A must be finite and >= 0");
+    if ((p.flags & EXS_FLAG_RESCORE2) && p.rank_keep <= 0)
+        return fail(EXS_EINVAL, "EXS_FLAG_RESCORE2 rescores the ranked poses: it needs rank_keep > 0");
     LaunchShape& sh = *out;
     sh.ppl = p.poses_per_lane ? p.poses_per_lane : 1;
-    if (sh.ppl != 1 && sh.ppl != 2) return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2", sh.ppl);
+    if (sh.ppl != 1 && sh.ppl != 2 && sh.ppl != 4)
+        return fail(EXS_EINVAL, "poses_per_lane %d: supported 1, 2, 4", sh.ppl);
     const int K = p.n_orient;
     sh.wpl = (K + kWave * sh.ppl - 1) / (kWave * sh.ppl);
     sh.lpw = p.ligands_per_wg;
     if (sh.lpw == 0) sh.lpw = std::max(1, std::min(kMaxLpw, kMaxWavesPerWg / std::max(1, sh.wpl) / 2));
     if (sh.lpw != 1 && sh.lpw != 2 && sh.lpw != 4 && sh.lpw != 8)
         return fail(EXS_EINVAL, "ligands_per_wg %d: supported 1, 2, 4, 8", sh.lpw);
-    sh.threads = sh.lpw * sh.wpl * kWave;
-    if (sh.threads > kMaxThreadsPerWg)
-        return fail(EXS_EINVAL, "workgroup of %d ligands x %d waves exceeds %d threads", sh.lpw, sh.wpl,
-                    kMaxThreadsPerWg);
     sh.top_k = std::min(p.top_k, K);
+    const int waves = dock_waves(sh.lpw, sh.wpl, sh.top_k, sh.ppl, p.torsion_steps);
+    if (waves < 1)
+        return fail(EXS_EINVAL, "tile of %d ligands x %d poses per lane does not fit in %zu B of LDS",
+                    sh.lpw, sh.ppl, kMaxLdsBytes);
+    sh.threads = waves * kWave;
     int storage = -1;
     for (size_t s = 0; s < b.pockets.size(); ++s) {
         auto pk = find_pocket(b.pockets[s]);
@@ -760,10 +810,7 @@ int launch_shape(const Batch& b, const exs_search_params& p, bool persistent, La
         storage = storage < 0 ? pk->storage : storage;
     }
     sh.storage = storage < 0 ? 0 : storage;
-    sh.lds = dock_lds_bytes(sh.lpw, sh.top_k, sh.lpw * sh.wpl, sh.ppl, p.torsion_steps);
-    if (sh.lds > kMaxLdsBytes)
-        return fail(EXS_EINVAL, "tile of %d ligands x %d waves x %d poses per lane needs %zu B of LDS (max %zu)",
-                    sh.lpw, sh.wpl, sh.ppl, sh.lds, kMaxLdsBytes);
+    sh.lds = dock_lds_bytes(sh.lpw, sh.top_k, waves, sh.ppl, p.torsion_steps);
     sh.fn = dock_kernel_fn(sh.storage, p.torsion_steps, sh.ppl);
     if (!sh.fn) return fail(EXS_EINVAL, "no kernel for this configuration");
     if (sh.lds > 64 * 1024) {
@@ -791,6 +838,10 @@ void base_args(DockArgs& a, const Batch& b, const exs_search_params& p, const La
     a.rank_thr2 = p.cluster_rmsd_A * p.cluster_rmsd_A;
     a.n_max = b.n_max;
     a.slot_floats = (int64_t)sh.lpw * a.n_max * 3 * a.kp;
+    a.rescore2 = (p.flags & EXS_FLAG_RESCORE2) ? 1 : 0;
+    a.rot_ac = b.d_rot_ac;
+    a.eps2 = EXS_RESCORE2_CONTACT_EPS;
+    a.w2 = EXS_RESCORE2_TORSION_W;
 }
 
 // Workgroups of a persistent launch of shape sh that are resident at once on device dev.
@@ -892,6 +943,9 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
                 (rc = job_alloc(al, &a.n_clusters, (size_t)L)) ||
                 (rc = job_alloc(al, &a.ranked, (size_t)L * p.rank_keep)) ||
                 (rc = job_alloc(al, &a.final_xyz, p.rank_keep > 0 ? (size_t)A * 3 * K : (size_t)0)) ||
+                (rc = job_alloc(al, &a.score2, a.rescore2 ? (size_t)L * p.rank_keep : (size_t)0)) ||
+                (rc = job_alloc(al, &a.best2_k, a.rescore2 ? (size_t)L : (size_t)0)) ||
+                (rc = job_alloc(al, &a.best2, a.rescore2 ? (size_t)L : (size_t)0)) ||
                 (rc = job_alloc(al, &a.tile_counter, (size_t)kMaxWorkQueues)) ||
                 (rc = job_alloc(al, &a.scratch, (size_t)std::max<int64_t>(slots, 1) * a.slot_floats))) {
                 free_allocs(al);
@@ -1028,6 +1082,26 @@ int exs_get_orientation_results(int64_t job, float* score, exs_pose_desc* desc) 
                 }
             }
         }
+        return EXS_OK;
+    } catch (const std::exception& e) {
+        return fail(EXS_ENOMEM, "exception: %s", e.what());
+    }
+}
+
+int exs_get_rescored_poses(int64_t job, int wait, double* score2, int32_t* best_orient,
+                           double* best_score2) {
+    try {
+        auto j = find_job(job);
+        if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+        const DockArgs& a = j->args;
+        if (!a.rescore2) return fail(EXS_EINVAL, "job %lld was run without EXS_FLAG_RESCORE2", (long long)job);
+        if (int rc = job_wait(*j, wait)) return rc;
+        if (score2)
+            if (int rc = copy_out(score2, a.score2, (size_t)j->L * a.rank_keep)) return rc;
+        if (best_orient)
+            if (int rc = copy_out(best_orient, a.best2_k, (size_t)j->L)) return rc;
+        if (best_score2)
+            if (int rc = copy_out(best_score2, a.best2, (size_t)j->L)) return rc;
         return EXS_OK;
     } catch (const std::exception& e) {
         return fail(EXS_ENOMEM, "exception: %s", e.what());

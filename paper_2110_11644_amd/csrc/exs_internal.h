@@ -160,6 +160,14 @@ struct DockArgs {
     int32_t* n_clusters;      // [L]
     int32_t* ranked;          // [L*rank_keep] orientation indices, leaders first
     float* final_xyz;         // [A*3][K] final pose of every orientation (rank_keep > 0)
+    // second-stage rescoring of the ranked poses (rescore2 > 0; needs rank_keep > 0)
+    int32_t rescore2;
+    int32_t pad2;
+    const uint32_t* rot_ac;   // [R] a | c << 16 (0xffff: none): dihedral neighbours of u and v
+    double eps2, w2;          // contact well depth, torsion weight of the second-stage score
+    double* score2;           // [L*rank_keep] second-stage score of each ranked pose
+    int32_t* best2_k;         // [L] orientation of the lowest second-stage score
+    double* best2;            // [L] that score
 };
 
 // LDS words per wave of the ranking kernel: rank, state and score per pose, the leader bits,
@@ -189,6 +197,14 @@ __host__ __device__ inline size_t dock_lds_bytes(int lpw, int top_k, int waves, 
     return dock_lds_diff_offset(lpw, top_k) + (size_t)waves * ppl * S * kWave * sizeof(int32_t);
 }
 constexpr size_t kMaxLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
+// Waves of a dock workgroup for a tile of lpw ligands x wpl orientation chunks: one per chunk
+// up to kMaxWavesPerWg, fewer if their clash difference arrays would not fit in LDS (the waves
+// then take the chunks in turn); 0 if not even one wave fits.
+__host__ __device__ inline int dock_waves(int lpw, int wpl, int top_k, int ppl, int S) {
+    int w = lpw * wpl < kMaxWavesPerWg ? lpw * wpl : kMaxWavesPerWg;
+    while (w > 0 && dock_lds_bytes(lpw, top_k, w, ppl, S) > kMaxLdsBytes) --w;
+    return w;
+}
 
 // Launchers (dock_misc.hip).
 hipError_t launch_dock(const DockArgs& a, int storage, int ppl, int n_blocks, int threads,
@@ -222,7 +238,11 @@ hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const 
                          hipStream_t st);
 // Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand.
 hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
+// Second-stage rescoring of the ranked poses of `n_lig` ligands, one wave per ligand.
+hipError_t launch_rescore2(const DockArgs& a, int n_lig, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+// *flag |= 1 if a texel is not finite, |= 2 if one overflows the 16-bit storage (storage 1, 2).
+hipError_t launch_check_texels(const float* v, int64_t count, int storage, int* flag, hipStream_t st);
 // K orientation matrices [K][9] (row-major), FP32 and (unless r64 is null) FP64.
 hipError_t launch_orientation_table(int K, float* r32, double* r64, hipStream_t st);
 hipError_t upload_trig_tables();

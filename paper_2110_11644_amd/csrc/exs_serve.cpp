@@ -5,8 +5,9 @@
 // (Sec. 3.2, 4.3).  Here one scheduler thread per server plays that role:
 //  * requests (a CSR ligand batch against resident pockets) are validated and
 //    packed on the submitting thread and queued;
-//  * admission: a request enters the device arena (ligand, atom and bond
-//    ranges, sized from the HBM budget) when its ranges fit -- FIFO, so a
+//  * admission: a request enters the device arena when its bytes fit in the
+//    HBM budget (the caller's, clamped to the device's free memory less a
+//    reserve) and its ligand, atom and bond ranges fit -- FIFO, so a
 //    request that does not fit holds back the ones behind it (backpressure);
 //    its packed data is uploaded on an upload stream;
 //  * iterations: each launch is the persistent dock kernel over a work list of
@@ -100,6 +101,7 @@ enum ReqState { kQueued, kInflight, kDone };
 struct Request {
     int64_t id = 0;
     int L = 0, A = 0, R = 0;
+    int64_t bytes = 0;          // device bytes it holds while admitted
     // packed host data (request-local bases)
     std::vector<LigInfo> info;
     std::vector<float4> ref;
@@ -169,6 +171,9 @@ class Server {
     DockArgs base_{};
     std::vector<void*> dev_bufs_;
     RangeAlloc lig_alloc_, atom_alloc_, rot_alloc_;
+    int64_t per_lig_ = 0, per_atom_ = 0, per_rot_ = 0;       // device bytes of each item
+    int64_t budget_ = 0, arena_budget_ = 0;                    // HBM budget; its request part
+    int64_t admitted_bytes_ = 0, peak_admitted_bytes_ = 0, peak_queued_ = 0;
     hipStream_t up_stream_ = nullptr;
     hipEvent_t up_event_ = nullptr;
     bool up_pending_ = false;
@@ -212,15 +217,16 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     if (p.top_k < 0 || p.top_k > EXS_MAX_TOPK) return rt::fail(EXS_EINVAL, "top_k %d", p.top_k);
     if (p.rank_keep != 0) return rt::fail(EXS_EINVAL, "the server does not rank poses (rank_keep must be 0)");
     ppl_ = p.poses_per_lane ? p.poses_per_lane : 1;
-    if (ppl_ != 1 && ppl_ != 2) return rt::fail(EXS_EINVAL, "poses_per_lane %d", ppl_);
+    if (ppl_ != 1 && ppl_ != 2 && ppl_ != 4) return rt::fail(EXS_EINVAL, "poses_per_lane %d", ppl_);
     wpl_ = (K_ + kWave * ppl_ - 1) / (kWave * ppl_);
     lpw_ = p.ligands_per_wg ? p.ligands_per_wg : 1;
-    if ((lpw_ != 1 && lpw_ != 2 && lpw_ != 4 && lpw_ != 8) || lpw_ * wpl_ * kWave > kMaxThreadsPerWg)
-        return rt::fail(EXS_EINVAL, "ligands_per_wg %d does not fit a workgroup", lpw_);
-    threads_ = lpw_ * wpl_ * kWave;
+    if (lpw_ != 1 && lpw_ != 2 && lpw_ != 4 && lpw_ != 8)
+        return rt::fail(EXS_EINVAL, "ligands_per_wg %d: supported 1, 2, 4, 8", lpw_);
     top_k_ = std::min(p.top_k, K_);
-    lds_ = dock_lds_bytes(lpw_, top_k_, lpw_ * wpl_, ppl_, p.torsion_steps);
-    if (lds_ > kMaxLdsBytes) return rt::fail(EXS_EINVAL, "tile needs %zu B of LDS", lds_);
+    const int waves = dock_waves(lpw_, wpl_, top_k_, ppl_, p.torsion_steps);
+    if (waves < 1) return rt::fail(EXS_EINVAL, "tile does not fit in LDS");
+    threads_ = waves * kWave;
+    lds_ = dock_lds_bytes(lpw_, top_k_, waves, ppl_, p.torsion_steps);
     n_iters_ = cfg.max_inflight_iters == 1 ? 1 : 2;
     // pockets
     std::vector<GridDesc> grids;
@@ -250,14 +256,27 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     res_theta_bytes_ = (size_t)EXS_MAX_ROT * max_iter_;
     const int64_t scratch_bytes = (int64_t)n_iters_ * resident_ * slot_floats * 4 +
                                   (int64_t)n_iters_ * (res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_);
-    const int64_t per_lig = 32 + 12LL * K_ + 40 + 28LL * top_k_ + 4;   // info, per-orientation, best, top-k, order
-    const int64_t per_atom = 16 + 24 + 16 + 12;
-    const int64_t per_rot = 4 + 16 + K_ + 1 + top_k_;
-    const int64_t unit = per_lig + 48 * per_atom + 16 * per_rot;      // 48 atoms, 16 bonds per ligand slot
-    const int64_t budget = cfg.hbm_budget_bytes > 0 ? cfg.hbm_budget_bytes : (int64_t)2 << 30;
-    const int64_t cap_l = (budget - scratch_bytes) / unit;
-    if (cap_l < 1) return rt::fail(EXS_ENOMEM, "HBM budget %lld below the iteration scratch (%lld)",
-                                   (long long)budget, (long long)scratch_bytes);
+    per_lig_ = 32 + 12LL * K_ + 40 + 28LL * top_k_ + 4;   // info, per-orientation, best, top-k, order
+    per_atom_ = 16 + 24 + 16 + 12;
+    per_rot_ = 4 + 16 + K_ + 1 + top_k_;
+    // budget: the caller's (2 GiB if 0), never more than the device's free memory less a reserve
+    // (1 GiB or 5 % of the device, the larger) for the rest of the process
+    size_t free_b = 0, total_b = 0;
+    SRV_TRY(hipMemGetInfo(&free_b, &total_b));
+    const int64_t reserve = std::max<int64_t>((int64_t)1 << 30, (int64_t)(total_b / 20));
+    const int64_t avail = std::max<int64_t>(0, (int64_t)free_b - reserve);
+    const int64_t asked = cfg.hbm_budget_bytes > 0 ? cfg.hbm_budget_bytes : (int64_t)2 << 30;
+    budget_ = std::min(asked, avail);
+    arena_budget_ = budget_ - scratch_bytes;
+    // index ranges of the arena: 1.5x the ligands, atoms and bonds of the byte budget at 48 atoms
+    // and 16 bonds per ligand, so that for usual ligand sizes the byte budget, not a range, is
+    // what admission runs out of (requests are admitted by their actual bytes)
+    const int64_t unit = per_lig_ + 48 * per_atom_ + 16 * per_rot_;
+    const int64_t cap_l = arena_budget_ > 0 ? (3 * arena_budget_) / (2 * unit) : 0;
+    if (cap_l < 1)
+        return rt::fail(EXS_ENOMEM, "HBM budget %lld (asked %lld, free %zu less %lld reserved) below "
+                        "the iteration scratch (%lld) and one ligand", (long long)budget_,
+                        (long long)asked, free_b, (long long)reserve, (long long)scratch_bytes);
     int64_t cap = std::min<int64_t>(cap_l, 1 << 24);
     if (cfg.max_arena_ligands > 0) cap = std::min<int64_t>(cap, cfg.max_arena_ligands);
     const int capL = (int)cap;
@@ -342,8 +361,11 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
     r->R = in.rot_offset[L];
     if (r->R > 0 && !in.rot_bond) return rt::fail(EXS_EINVAL, "null rot_bond");
     if (in.bond_offset[L] > 0 && !in.bond_ij) return rt::fail(EXS_EINVAL, "null bond_ij");
-    if (r->L > lig_alloc_.cap() || r->A > atom_alloc_.cap() || r->R > rot_alloc_.cap())
-        return rt::fail(EXS_ENOMEM, "request of %d ligands / %d atoms exceeds the server arena", L, r->A);
+    r->bytes = (int64_t)r->L * per_lig_ + (int64_t)r->A * per_atom_ + (int64_t)r->R * per_rot_;
+    if (r->L > lig_alloc_.cap() || r->A > atom_alloc_.cap() || r->R > rot_alloc_.cap() ||
+        r->bytes > arena_budget_)
+        return rt::fail(EXS_ENOMEM, "request of %d ligands / %d atoms (%lld B) exceeds the server arena "
+                        "(%lld B)", L, r->A, (long long)r->bytes, (long long)arena_budget_);
     r->info.resize(L); r->ref.resize(r->A); r->ref64.resize((size_t)r->A * 3); r->excl.resize(r->A);
     r->ruv.resize(r->R); r->rmask.resize(r->R); r->cost.resize(L);
     r->best_score.resize(L); r->desc.resize(L); r->coords.resize((size_t)r->A * 3);
@@ -393,6 +415,7 @@ int Server::submit(const exs_ligand_batch& in, int64_t* id_out) {
     r->t_submit = Clock::now();
     *id_out = r->id;
     queue_.push_back(r.get());
+    peak_queued_ = std::max<int64_t>(peak_queued_, (int64_t)queue_.size());
     reqs_[r->id] = std::move(r);
     submitted_++;
     cv_.notify_all();
@@ -405,12 +428,15 @@ bool Server::admit_locked() {
     while (!queue_.empty()) {
         Request* r = queue_.front();
         int l0, a0, r0;
+        if (admitted_bytes_ + r->bytes > arena_budget_) break;   // the byte budget holds it back
         if (!lig_alloc_.alloc(r->L, &l0)) break;
         if (!atom_alloc_.alloc(r->A, &a0)) { lig_alloc_.release(l0, r->L); break; }
         if (!rot_alloc_.alloc(r->R, &r0)) {
             lig_alloc_.release(l0, r->L); atom_alloc_.release(a0, r->A); break;
         }
         queue_.pop_front();
+        admitted_bytes_ += r->bytes;
+        peak_admitted_bytes_ = std::max(peak_admitted_bytes_, admitted_bytes_);
         r->lig0 = l0; r->atom0 = a0; r->rot0 = r0;
         for (auto& inf : r->info) { inf.atom_base += a0; inf.rot_base += r0; }
         const DockArgs& a = base_;
@@ -555,6 +581,7 @@ void Server::complete(Iteration& it) {
         lig_alloc_.release(r->lig0, r->L);
         atom_alloc_.release(r->atom0, r->A);
         rot_alloc_.release(r->rot0, r->R);
+        admitted_bytes_ -= r->bytes;
         r->state = kDone;
         r->t_done = Clock::now();
         completed_++;
@@ -640,6 +667,11 @@ void Server::stats(exs_server_stats* out) {
     out->arena_ligands = lig_alloc_.cap();
     out->arena_atoms = atom_alloc_.cap();
     out->busy_ms = busy_ms_;
+    out->budget_bytes = budget_;
+    out->arena_budget_bytes = arena_budget_;
+    out->admitted_bytes = admitted_bytes_;
+    out->peak_admitted_bytes = peak_admitted_bytes_;
+    out->peak_queued = peak_queued_;
 }
 
 void Server::shutdown() {

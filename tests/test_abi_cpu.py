@@ -111,3 +111,31 @@ def test_invalid_ligands_are_rejected(B, case):
     with pytest.raises(B.ExsError) as ei:
         B.exs_pack_topology(lig, channels)
     assert ei.value.code == B.EXS_EINVAL
+
+
+@pytest.mark.parametrize("storage,bad,good", [
+    (2, 65520.0, 65519.996),          # FP16: 65520 is the tie above 65504 and rounds to inf
+    (1, float(np.uint32(0x7f7f8000).view(np.float32)),   # BF16: the tie above the largest
+     float(np.uint32(0x7f7f7fff).view(np.float32))),     # finite BF16 rounds to inf
+])
+def test_texels_that_overflow_16bit_storage_are_refused(B, storage, bad, good):
+    """A finite FP32 texel that rounds (to nearest even) to infinity in the requested 16-bit
+    storage is refused with EXS_EINVAL before any device work; numpy's own rounding of the same
+    values confirms the thresholds (FP16), and a value just below passes validation."""
+    if storage == 2:
+        assert np.isinf(np.float16(np.float32(bad))) and np.isfinite(np.float16(np.float32(good)))
+    vals = np.zeros((1, 2, 2, 2), np.float32)
+    vals[0, 1, 1, 1] = bad
+    with pytest.raises(B.ExsError) as ei:
+        B.exs_load_pocket_grid(vals, 0.5, np.zeros(3), storage)
+    assert ei.value.code == B.EXS_EINVAL and "overflows" in str(ei.value)
+    vals[0, 1, 1, 1] = -bad
+    with pytest.raises(B.ExsError) as ei:
+        B.exs_load_pocket_grid(vals, 0.5, np.zeros(3), storage)
+    assert ei.value.code == B.EXS_EINVAL
+    vals[0, 1, 1, 1] = good
+    try:
+        pid = B.exs_load_pocket_grid(vals, 0.5, np.zeros(3), storage)
+        B.exs_unload_pocket(pid)
+    except B.ExsError as e:            # no GPU here: validation passed, the device call failed
+        assert e.code != B.EXS_EINVAL, str(e)

@@ -112,6 +112,30 @@ def test_tile_configs_and_persistent_are_bitwise_identical(B, small):
                 assert np.array_equal(a, b)
 
 
+def test_every_tile_of_the_tuner_is_bitwise_identical(B, small):
+    """All twelve (poses per lane, ligands per workgroup) tiles at 256 orientations and 32
+    torsion steps, one launch per pocket and persistent: the tiles with more orientation chunks
+    than a workgroup has waves (ligands per workgroup 4 and 8 at one or two poses per lane), and
+    four poses per lane, whose LDS difference arrays cap the workgroup's waves, give the results
+    of (1, 1) bit for bit."""
+    p, g, batch = small
+    s = S.SearchSettings(256, 32, 1, 27)
+    sub = batch.subset(range(20))
+    ref = None
+    for ppl in (1, 2, 4):
+        for lpw in (1, 2, 4, 8):
+            for flags in (0, B.EXS_FLAG_PERSISTENT):
+                log("tile ppl=%d lpw=%d flags=%d" % (ppl, lpw, flags))
+                out = run(B, [p], sub, s, ppl=ppl, lpw=lpw, flags=flags)
+                key = (out["score"], out["desc"]["theta"], out["desc"]["tau"], out["coords"],
+                       out["best_score"])
+                if ref is None:
+                    ref = key
+                else:
+                    for a, b in zip(ref, key):
+                        assert np.array_equal(a, b), (ppl, lpw, flags)
+
+
 def test_orientation_count_not_a_multiple_of_64(B, oracle_lib, small):
     O = oracle_lib
     p, g, batch = small

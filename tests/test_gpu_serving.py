@@ -280,3 +280,46 @@ def test_served_16bit_topk_matches_oracle(B, oracle_lib):
                     l, d["score_fp64"], d["orient"], b64, k64)
                 n_amb += 1
     log("served 16-bit ligands:", sum(r.n_ligands for r in reqs), "accepted on a near tie:", n_amb)
+
+
+def request_bytes(r, K, top_k=0):
+    """Device bytes a request holds while admitted (the formula exs.h states)."""
+    return (r.n_ligands * (76 + 12 * K + 28 * top_k) + 68 * int(r.atom_offset[-1])
+            + int(r.rot_offset[-1]) * (21 + K + top_k))
+
+
+def test_byte_budget_holds_requests_back(B, setup):
+    """A server whose HBM budget leaves room for about two requests' bytes beyond its iteration
+    scratch: with all 12 requests submitted at once, some wait for admission (backpressure),
+    the admitted bytes never exceed the budget, and every result equals the unconstrained
+    server's.  The default budget is clamped to the device's free memory."""
+    import torch
+    pids, reqs = setup
+    srv = B.exs_server_create(pids, params(B))
+    st = B.exs_server_get_stats(srv)
+    B.exs_server_destroy(srv)
+    free, total = torch.cuda.mem_get_info()
+    assert 0 < st["budget_bytes"] <= free
+    scratch = st["budget_bytes"] - st["arena_budget_bytes"]
+    big = max(request_bytes(r, WL.search.n_orient) for r in reqs)
+    budget = scratch + 2 * big + big // 2
+    log("budget %d B: iteration scratch %d B + %d B for requests (largest %d B)" % (
+        budget, scratch, budget - scratch, big))
+    res, stats = serve(B, pids, reqs, hbm_budget_bytes=budget)
+    log("stats", stats)
+    assert stats["budget_bytes"] == budget and stats["arena_budget_bytes"] == budget - scratch
+    assert stats["completed"] == len(reqs)
+    assert stats["peak_queued"] >= 1
+    assert 0 < stats["peak_admitted_bytes"] <= budget - scratch
+    assert stats["admitted_bytes"] == 0
+    ref, _ = serve(B, pids, reqs)
+    for i in range(len(reqs)):
+        assert np.array_equal(ref[i]["best_score"], res[i]["best_score"])
+        assert np.array_equal(ref[i]["coords"], res[i]["coords"])
+    with pytest.raises(B.ExsError) as ei:        # a request larger than the byte budget
+        srv = B.exs_server_create(pids, params(B), hbm_budget_bytes=scratch + big // 2)
+        try:
+            B.exs_server_submit(srv, max(reqs, key=lambda r: request_bytes(r, 64)), pocket_ids=pids)
+        finally:
+            B.exs_server_destroy(srv)
+    assert ei.value.code == B.EXS_ENOMEM
