@@ -109,7 +109,14 @@ def cpu_baseline(workload, pocket, batch, search, max_ligands=1024, budget_s=20.
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": done / dt, "unit": "docks/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
             "sample": "first %d ligands of the %s workload (same pocket and search settings), "
                       "FP64 oracle, OpenMP over ligands, %.1f s" % (done, workload, dt)}
 
@@ -166,18 +173,25 @@ def gather_probe(B, pid, storage, stream, batch, search, channels, kernel_ms,
     dock_lookups = search.n_orient * Lk.sum() * batch.n_ligands / sub.n_ligands
     out = {"lookups_per_launch": lanes * per_lane,
            "texel_bytes_per_lookup": 32 if storage == 0 else 16}
-    for name, half in (("cube_6A", 3.0), ("cube_20A", 10.0)):
+    # independent points in a 6 A and a 20 A cube; walks in the 6 A cube with steps of at most
+    # 0.1 / 0.25 A per axis (the docking lookups' locality: the turns of an atom lie 0.27 A apart
+    # on a circle, the 27 offsets of an atom in a 1 A cube)
+    for name, half, walk in (("cube_6A", 3.0, 0.0), ("cube_20A", 10.0, 0.0),
+                             ("walk_0.25A", 3.0, 0.25), ("walk_0.1A", 3.0, 0.1)):
         best = None
         for nb in (8, 16):
-            B.exs_gather_probe(pid, lanes, per_lane, half, 0.0, 7, batch=nb, stream=stream)   # warm
-            ms, _ = B.exs_gather_probe(pid, lanes, per_lane, half, 0.0, 11, batch=nb, stream=stream)
+            B.exs_gather_probe(pid, lanes, per_lane, half, walk, 7, batch=nb, stream=stream)   # warm
+            ms, _ = B.exs_gather_probe(pid, lanes, per_lane, half, walk, 11, batch=nb, stream=stream)
             rate = lanes * per_lane / (ms * 1e-3)
             if best is None or rate > best[1]:
                 best = (ms, rate, nb)
         out[name] = {"ms": round(best[0], 3), "lookups_per_s": round(best[1], 0), "in_flight": best[2]}
     out["dock_lookups_per_s"] = round(dock_lookups / (kernel_ms * 1e-3), 0)
-    out["dock_frac_of_cube_6A"] = round(out["dock_lookups_per_s"] / out["cube_6A"]["lookups_per_s"], 3)
-    out["dock_frac_of_cube_20A"] = round(out["dock_lookups_per_s"] / out["cube_20A"]["lookups_per_s"], 3)
+    for name in ("cube_6A", "cube_20A", "walk_0.25A", "walk_0.1A"):
+        out["dock_frac_of_" + name] = round(out["dock_lookups_per_s"] / out[name]["lookups_per_s"], 3)
+    top = max(("cube_6A", "cube_20A", "walk_0.25A", "walk_0.1A"), key=lambda n: out[n]["lookups_per_s"])
+    out["ceiling"] = top
+    out["dock_frac_of_ceiling"] = out["dock_frac_of_" + top]
     progress("gather probe: %s" % out)
     return out
 
@@ -953,6 +967,8 @@ def main():
         # not the value: the same steps with the host-side ligand upload (packing + PCIe) added
         "host_inclusive": {"upload_ms": round(upload_s * 1e3, 2),
                            "docks_per_s": round(L / (upload_s + dt / args.steps), 2)},
+        # identifies the results (runs with equal results print the same digest)
+        "best_scores_sha256": __import__("hashlib").sha256(out["best_score"].tobytes()).hexdigest()[:16],
     }
     if extra is not None:
         legs = extra["legs"]
