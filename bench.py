@@ -818,6 +818,8 @@ def main():
     ap.add_argument("--rank-keep", type=int, default=0,
                     help="scale/small: rank each ligand's final poses and keep this many (0 = off)")
     ap.add_argument("--cluster-rmsd", type=float, default=3.0, help="ranking: RMSD threshold (A)")
+    ap.add_argument("--rescore2", action="store_true",
+                    help="scale/small with --rank-keep: rescore the ranked poses (second stage)")
     ap.add_argument("--unfold-passes", type=int, default=0,
                     help="scale/small: unfold the ligands first (passes; 0 = off), timed apart")
     ap.add_argument("--requests", type=int, default=1000, help="serving: timed requests")
@@ -891,6 +893,8 @@ def main():
         unfold_ms = (time.perf_counter() - t_uf) * 1e3
         progress("unfolded %d ligands (%d passes): %.2f ms" % (batch.n_ligands, args.unfold_passes, unfold_ms))
     flags = B.EXS_FLAG_PERSISTENT if args.persistent else 0
+    if args.rescore2 and args.rank_keep > 0:
+        flags |= B.EXS_FLAG_RESCORE2
     prm = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                           s.clash_cutoff, s.clash_penalty, top_k=0, poses_per_lane=args.ppl,
                           ligands_per_wg=args.lpw, flags=flags, cluster_rmsd_A=args.cluster_rmsd,
@@ -959,6 +963,7 @@ def main():
             "ligands": L, "atoms": A, "parallelism": "single GPU",
             "poses_per_lane": args.ppl, "ligands_per_wg": args.lpw,
             "rank_keep": args.rank_keep, "cluster_rmsd_A": args.cluster_rmsd if args.rank_keep else None,
+            "rescore2": bool(args.rescore2 and args.rank_keep > 0),
             "unfold_passes": args.unfold_passes, "unfold_ms": None if unfold_ms is None else round(unfold_ms, 3),
         },
         "roofline": roof,

@@ -146,10 +146,11 @@ int exs_get_rescored_poses(int64_t job, int wait, double* score2, int32_t* best_
  * (Sec. 3.1: the score of a pose is a lookup per atom in the pocket's grids).
  * n_lanes lanes (rounded up to a multiple of 256) each do lookups_per_lane lookups (rounded
  * up to a multiple of batch), issued `batch` (8, 16 or 32) at a time independently of each
- * other, at 4, 3 or 2 waves per SIMD respectively, at
- * pseudo-random points of the cube of half edge half_edge_A (A) around the pocket centre:
- * independent points when walk_step_A = 0, else a walk of at most walk_step_A per axis and
- * step, clamped to the cube.  Channels cycle per lookup.  Runs on `stream` and waits for it.
+ * other, at 4, 3 or 2 waves per SIMD respectively, in runs of 32 lookups like the search's
+ * lookups of one atom: a run keeps one channel (the next run takes the next) and starts at a
+ * pseudo-random point of the cube of half edge half_edge_A (A) around the pocket centre; its
+ * further points are independent points of the cube when walk_step_A = 0, else a walk of at
+ * most walk_step_A per axis and step, clamped to the cube.  Runs on `stream` and waits for it.
  *   ms_out        device time of the probe kernel (HIP events).
  *   checksum_out  sum of the lanes' lookup sums (may be NULL).
  * Errors: EXS_EINVAL (sizes, batch, non-finite or negative lengths, pocket on another device),

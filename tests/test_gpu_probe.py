@@ -50,7 +50,8 @@ def probe_points(pocket, n_lanes, per_lane, half_A, seed):
     for i in range(per_lane):
         pts[:, i, :] = np.stack(p, axis=1)
         chans[:, i] = c
-        c = np.where(c + 1 == C, 0, c + 1)
+        if (i + 1) % 32 == 0:                  # runs of 32 lookups keep one channel
+            c = np.where(c + 1 == C, 0, c + 1)
         h = mix32(h + np.uint64(0x9e3779b9))
         p = coords(h)
     return pts, chans
@@ -64,7 +65,7 @@ def test_gather_probe_sum_matches_oracle(oracle_lib):
     pocket = S.make_pocket("small")
     pid = B.exs_load_pocket_grid(pocket.values, pocket.spacing, pocket.origin, B.STORAGE["f32"])
     try:
-        n_lanes, per_lane, half, seed = 512, 32, 9.0, 12345
+        n_lanes, per_lane, half, seed = 512, 96, 9.0, 12345
         ms, chk = B.exs_gather_probe(pid, n_lanes, per_lane, half, 0.0, seed)
         assert ms > 0.0
         pts, chans = probe_points(pocket, n_lanes, per_lane, half, seed)
