@@ -789,6 +789,14 @@ def driver_legs(args, torch, S, B):
                                   poses_per_lane=1, ligands_per_wg=1, flags=B.EXS_FLAG_PERSISTENT)
             srv[name] = serve_trace(B, pids, prm, trace, reqs, warm_req)
             progress("%s: %s" % (name, srv[name]))
+            if storage == 1:
+                # the same requests at 0.7 x the mixed-precision form's own capacity (arrival
+                # times compressed by the ratio of the capacities)
+                own = legs["persistent_bf16_top8"]["docks_per_s"]
+                srv[name + "_own_load"] = dict(
+                    serve_trace(B, pids, prm, trace, reqs, warm_req, time_scale=cap / own),
+                    offered_docks_per_s=round(args.load * own, 1))
+                progress("%s at its own load: %s" % (name, srv[name + "_own_load"]))
             if storage == 0:
                 prm_p = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets,
                                         s.offset_step, s.clash_cutoff, s.clash_penalty,
@@ -991,6 +999,9 @@ def main():
             "served_f32": pick(line["served"]["served_f32"], "docks_per_s", "p50_ms", "p99_ms"),
             "served_bf16_top8": pick(line["served"]["served_bf16_top8"], "docks_per_s", "p50_ms",
                                      "p99_ms"),
+            "served_bf16_top8_own_load": pick(line["served"]["served_bf16_top8_own_load"],
+                                              "docks_per_s", "p50_ms", "p99_ms",
+                                              "offered_docks_per_s"),
             "plain_per_request_f32": pick(line["served"]["plain_per_request_f32"], "docks_per_s",
                                           "p50_ms", "p99_ms", "workers"),
         }

@@ -282,8 +282,13 @@ typedef struct {
 
 /*
  * Dock every ligand of an uploaded batch against its pocket, asynchronously
- * on `stream`.  One launch per pocket (default), or one persistent launch
- * over all pockets (EXS_FLAG_PERSISTENT).  job_out receives the handle.
+ * on `stream` (Sec. 3.1: per ligand, restarts from the initial orientations,
+ * each a greedy optimisation of the torsions and the rigid roto-translation
+ * driven by the pocket score; the ligand's score is its best pose's; Sec. 3.2:
+ * every ligand x pocket pair is independent).  One launch per pocket (default),
+ * or one persistent launch over all pockets (EXS_FLAG_PERSISTENT).  job_out
+ * receives the handle.  The batch and its pockets must stay loaded until the job
+ * is released.
  * Errors: EXS_EINVAL (settings), EXS_ENOENT (unknown batch or a pocket
  * unloaded since upload), EXS_ENOMEM, EXS_EDEVICE.
  */
@@ -410,10 +415,11 @@ int exs_server_destroy(int64_t server);
  * The paper's docking application is a pipeline of a reader, a splitter, docking workers and a
  * writer joined by queues, which keeps the GPUs fed while the host prepares ligands (Sec. 3.2,
  * several workers per GPU in Sec. 4.3).  exs_campaign_run does that on one device for a library
- * in host memory: it validates every ligand and computes its search cost on `packers` host
- * threads, cuts the library, most costly ligands first, into chunks of chunk_ligands, and
- * streams the chunks through a server (exs_server_*) configured by `server`: packer threads
- * pack and submit chunks while earlier ones dock.  It returns when every ligand is docked.
+ * in host memory: it validates every ligand and computes its search cost on the host's
+ * threads, cuts the library, most costly ligands first, into chunks of chunk_ligands (the
+ * first one an eighth of that, at least 1,024, so the device starts early), and streams the
+ * chunks through a server (exs_server_*) configured by `server`: `packers` threads pack and
+ * submit chunks while earlier ones dock.  It returns when every ligand is docked.
  */
 typedef struct {
     int32_t chunk_ligands;      /* ligands per chunk (0: 16384)                              */

@@ -3,10 +3,11 @@
 // The paper's docking application is a pipeline -- a reader, a splitter, dockers and a
 // writer joined by queues -- that keeps the GPUs fed while the host prepares the next ligands
 // (Sec. 3.2), with several docking workers per GPU (Sec. 4.3).  Here, on one device:
-//  * the library is validated and every ligand's search cost computed on host threads (the
-//    exact lookup / pair-test count of its search); the ligands are then cut, most costly
-//    first, into chunks, so that the last launches hold the cheapest ligands and the device
-//    finishes evenly;
+//  * the library is validated and every ligand's search cost computed on all host threads
+//    (the exact lookup / pair-test count of its search); the ligands are then cut, most costly
+//    first, into chunks (a small first one, so that the device starts while the next are
+//    packed), so that the last launches hold the cheapest ligands and the device finishes
+//    evenly;
 //  * packer threads gather chunks into CSR requests and submit them to a server, which packs
 //    each on the submitting thread and docks the admitted requests in iterations of the
 //    persistent kernel while the next chunks are being packed;
@@ -138,8 +139,10 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
                                           params->torsion_steps, params->passes, params->n_offsets);
                 }
             };
+            // every host thread: nothing docks until this pass is done
+            const int nth = std::max<int>(packers, std::min<int>(32, (int)std::thread::hardware_concurrency()));
             std::vector<std::thread> pool;
-            for (int t = 1; t < packers; ++t) pool.emplace_back(work);
+            for (int t = 1; t < nth; ++t) pool.emplace_back(work);
             work();
             for (auto& t : pool) t.join();
         }
@@ -149,7 +152,13 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
         std::vector<int32_t> order(L);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        const int n_chunks = (L + chunk - 1) / chunk;
+        // chunk c covers order[start[c], start[c+1]): a first chunk of chunk/8 (at least 1,024)
+        // ligands gets the device going while the next chunks are packed
+        std::vector<int> start(1, 0);
+        const int first = std::min(L, std::max(std::min(chunk, 1024), chunk / 8));
+        if (L > 0) start.push_back(first);
+        while (start.back() < L) start.push_back(std::min(L, start.back() + chunk));
+        const int n_chunks = (int)start.size() - 1;
         int64_t server = 0;
         if (int rc = exs_server_create(pocket_ids, n_pockets, params, &cfg->server, &server)) return rc;
         std::vector<Chunk> chunks(n_chunks);
@@ -162,8 +171,7 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             for (;;) {
                 const int c = next.fetch_add(1);
                 if (c >= n_chunks) return;
-                const int a = c * chunk, n = std::min(chunk, L - a);
-                gather_chunk(lib, order.data() + a, n, chunks[c]);
+                gather_chunk(lib, order.data() + start[c], start[c + 1] - start[c], chunks[c]);
                 const exs_ligand_batch view = chunks[c].view();
                 int64_t h = 0;
                 const int rc = exs_server_submit(server, &view, &h);
