@@ -417,9 +417,10 @@ int exs_server_destroy(int64_t server);
  * several workers per GPU in Sec. 4.3).  exs_campaign_run does that on one device for a library
  * in host memory: it validates every ligand and computes its search cost on the host's
  * threads, cuts the library, most costly ligands first, into chunks of chunk_ligands (the
- * first one an eighth of that, at least 1,024, so the device starts early), and streams the
- * chunks through a server (exs_server_*) configured by `server`: `packers` threads pack and
- * submit chunks while earlier ones dock.  It returns when every ligand is docked.
+ * first ones 1,024, 2,048, ... ligands, doubling up to that, so the device starts early), and
+ * streams the chunks through a server (exs_server_*, created while the library is validated)
+ * configured by `server`: `packers` threads pack and submit chunks while earlier ones dock.  It
+ * returns when every ligand is docked.
  */
 typedef struct {
     int32_t chunk_ligands;      /* ligands per chunk (0: 16384)                              */
@@ -433,6 +434,8 @@ typedef struct {
     int64_t ligands, chunks, iterations;
     int32_t hits, pad;
     double seconds;             /* wall time of the call */
+    double prepass_seconds;     /* of it, the validation and cost pass over the library */
+    double first_submit_seconds;/* call start to the first chunk submitted */
 } exs_campaign_stats;
 
 /* Screen `library` (host CSR batch; pocket_id = handles among pocket_ids, all of one texel

@@ -81,7 +81,8 @@ class exs_campaign_config(C.Structure):
 
 class exs_campaign_stats(C.Structure):
     _fields_ = [("ligands", C.c_int64), ("chunks", C.c_int64), ("iterations", C.c_int64),
-                ("hits", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double)]
+                ("hits", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double),
+                ("prepass_seconds", C.c_double), ("first_submit_seconds", C.c_double)]
 
 
 # numpy view of exs_pose_desc (56 bytes, natural alignment)

@@ -96,45 +96,6 @@ __global__ void expand_grid_kernel(const float* __restrict__ src, uint4* __restr
     }
 }
 
-// One workgroup per ligand j of a serving iteration: copy its best-pose results (score,
-// orientation, offsets, FP64 score, coordinates, torsion bytes) from the arena to staging.
-__global__ void gather_results_kernel(const int32_t* __restrict__ lig, const int32_t* __restrict__ atom_dst,
-                                      const int32_t* __restrict__ rot_dst, int n,
-                                      const LigInfo* __restrict__ info, const float* __restrict__ best_score,
-                                      const int32_t* __restrict__ best_k, const int32_t* __restrict__ best_tau,
-                                      const double* __restrict__ best_score64,
-                                      const uint8_t* __restrict__ best_theta,
-                                      const float* __restrict__ best_coords, ResultRec* __restrict__ rec,
-                                      float* __restrict__ coords, uint8_t* __restrict__ theta) {
-    const int j = blockIdx.x;
-    if (j >= n) return;
-    const int l = lig[j];
-    const LigInfo inf = info[l];
-    if (threadIdx.x == 0) {
-        ResultRec r;
-        r.score = best_score[l];
-        r.k = best_k[l];
-        r.tau = best_tau[l];
-        r.pad = 0;
-        r.score64 = best_score64[l];
-        rec[j] = r;
-    }
-    const float* src = best_coords + (size_t)inf.atom_base * 3;
-    float* dst = coords + (size_t)atom_dst[j] * 3;
-    for (int i = threadIdx.x; i < 3 * inf.n; i += blockDim.x) dst[i] = src[i];
-    for (int b = threadIdx.x; b < inf.nrot; b += blockDim.x) theta[rot_dst[j] + b] = best_theta[inf.rot_base + b];
-}
-
-hipError_t launch_gather_results(const int32_t* lig, const int32_t* atom_dst, const int32_t* rot_dst,
-                                 int n, const DockArgs& a, ResultRec* rec, float* coords,
-                                 uint8_t* theta, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_results_kernel, dim3(n), dim3(128), 0, st, lig, atom_dst, rot_dst, n,
-                       a.info, a.best_score, a.best_k, a.best_tau, a.best_score64, a.best_theta,
-                       a.best_coords, rec, coords, theta);
-    return hipGetLastError();
-}
-
 // Zero a small int array with a kernel (safe inside a captured graph).
 __global__ void zero_ints_kernel(int* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -249,6 +210,23 @@ hipError_t launch_check_texels(const float* v, int64_t count, int storage, int* 
 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+__global__ void stage_ints_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n,
+                                  int* __restrict__ zero, int nz, int lig, int n_lig,
+                                  int32_t* __restrict__ slot) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nz) zero[t] = 0;
+    for (int i = t; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+    for (int j = t; j < n_lig; j += gridDim.x * blockDim.x) slot[src[lig + j]] = j;
+}
+
+hipError_t launch_stage_ints(const int32_t* src, int32_t* dst, int n, int* zero, int nz, int lig,
+                             int n_lig, int32_t* slot, hipStream_t st) {
+    const int blocks = std::max(1, std::min(256, (std::max(n, nz) + 255) / 256));
+    hipLaunchKernelGGL(stage_ints_kernel, dim3(blocks), dim3(256), 0, st, src, dst, n, zero, nz, lig,
+                       n_lig, slot);
     return hipGetLastError();
 }
 

@@ -4,10 +4,10 @@
 // writer joined by queues -- that keeps the GPUs fed while the host prepares the next ligands
 // (Sec. 3.2), with several docking workers per GPU (Sec. 4.3).  Here, on one device:
 //  * the library is validated and every ligand's search cost computed on all host threads
-//    (the exact lookup / pair-test count of its search); the ligands are then cut, most costly
-//    first, into chunks (a small first one, so that the device starts while the next are
-//    packed), so that the last launches hold the cheapest ligands and the device finishes
-//    evenly;
+//    (the exact lookup / pair-test count of its search) while the server is created; the
+//    ligands are then cut, most costly first, into chunks (the first ones small and growing,
+//    so that the device starts while the next are packed), so that the last launches hold the
+//    cheapest ligands and the device finishes evenly;
 //  * packer threads gather chunks into CSR requests and submit them to a server, which packs
 //    each on the submitting thread and docks the admitted requests in iterations of the
 //    persistent kernel while the next chunks are being packed;
@@ -102,6 +102,14 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
                 return rt::fail(EXS_EINVAL, "unknown pocket %d", pocket_ids[p]);
             channels[p] = info.channels;
         }
+        // the server is created (device buffers, streams) while the host threads validate
+        int64_t server = 0;
+        int create_rc = EXS_OK;
+        std::string create_err;
+        std::thread creator([&] {
+            create_rc = exs_server_create(pocket_ids, n_pockets, params, &cfg->server, &server);
+            if (create_rc != EXS_OK) create_err = exs_last_error();
+        });
         // validate every ligand and take its search cost (host threads)
         std::vector<double> cost(L, 0.0);
         std::vector<int> rc_of(L, EXS_OK);
@@ -146,27 +154,31 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             work();
             for (auto& t : pool) t.join();
         }
+        const auto t_pre = std::chrono::steady_clock::now();
+        creator.join();
         for (int l = 0; l < L; ++l)
-            if (rc_of[l]) return rt::fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
+            if (rc_of[l]) {
+                if (create_rc == EXS_OK) (void)exs_server_destroy(server);
+                return rt::fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
+            }
+        if (create_rc != EXS_OK) return rt::fail(create_rc, "%s", create_err.c_str());
         // most costly first; chunks cut from that order
         std::vector<int32_t> order(L);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        // chunk c covers order[start[c], start[c+1]): a first chunk of chunk/8 (at least 1,024)
-        // ligands gets the device going while the next chunks are packed
+        // chunk c covers order[start[c], start[c+1]): the first chunks grow from 1,024 ligands,
+        // doubling up to `chunk`, so that the device starts while the larger ones are packed
         std::vector<int> start(1, 0);
-        const int first = std::min(L, std::max(std::min(chunk, 1024), chunk / 8));
-        if (L > 0) start.push_back(first);
-        while (start.back() < L) start.push_back(std::min(L, start.back() + chunk));
+        for (int size = std::min(chunk, 1024); start.back() < L; size = std::min(chunk, 2 * size))
+            start.push_back((int)std::min<int64_t>(L, (int64_t)start.back() + size));
         const int n_chunks = (int)start.size() - 1;
-        int64_t server = 0;
-        if (int rc = exs_server_create(pocket_ids, n_pockets, params, &cfg->server, &server)) return rc;
         std::vector<Chunk> chunks(n_chunks);
         std::vector<int64_t> handle(n_chunks, 0);
         std::vector<int> state(n_chunks, 0);          // 0 pending, 1 submitted, < 0 failed
         std::mutex mu;
         std::condition_variable cv;
         std::atomic<int> next{0};
+        std::chrono::steady_clock::time_point t_first = t_pre;
         auto packer = [&]() {
             for (;;) {
                 const int c = next.fetch_add(1);
@@ -176,6 +188,7 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
                 int64_t h = 0;
                 const int rc = exs_server_submit(server, &view, &h);
                 std::lock_guard<std::mutex> lk(mu);
+                if (c == 0) t_first = std::chrono::steady_clock::now();
                 handle[c] = h;
                 state[c] = rc == EXS_OK ? 1 : rc;
                 cv.notify_all();
@@ -233,6 +246,8 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             stats->iterations = ss.iterations;
             stats->hits = n_hits;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            stats->prepass_seconds = std::chrono::duration<double>(t_pre - t0).count();
+            stats->first_submit_seconds = std::chrono::duration<double>(t_first - t0).count();
         }
         return EXS_OK;
     } catch (const std::exception& e) {

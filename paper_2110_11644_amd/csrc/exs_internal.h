@@ -104,6 +104,16 @@ struct GridDesc {
 };
 
 // Everything one dock launch reads and writes.
+// Serving: the results of one iteration's ligands in contiguous host memory (one record per
+// ligand, then coordinates and torsion bytes at host-computed offsets).
+struct ResultRec {
+    float score;
+    int32_t k;
+    int32_t tau;
+    int32_t pad;
+    double score64;
+};
+
 struct DockArgs {
     // packed ligand batch
     const LigInfo* info;
@@ -168,6 +178,16 @@ struct DockArgs {
     double* score2;           // [L*rank_keep] second-stage score of each ranked pose
     int32_t* best2_k;         // [L] orientation of the lowest second-stage score
     double* best2;            // [L] that score
+    // serving iterations (res_rec non-null): each ligand's finish also writes its result to the
+    // iteration's result buffer (mapped host memory), at position j = res_slot[l]: the record
+    // res_rec[j], coordinates from res_coords + 3 res_adst[j], torsion bytes from
+    // res_theta + res_rdst[j]; no kernel runs after the search
+    const int32_t* res_slot;  // [L] position of each ligand in its iteration's work list
+    const int32_t* res_adst;  // [work list]
+    const int32_t* res_rdst;  // [work list]
+    ResultRec* res_rec;
+    float* res_coords;
+    uint8_t* res_theta;
 };
 
 // LDS words per wave of the ranking kernel: rank, state and score per pose, the leader bits,
@@ -219,18 +239,6 @@ hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int n
 // (8, 16 or 32) independent lookups per round.
 hipError_t launch_gather_probe(const GridDesc* gd, int storage, int nb, int64_t blocks, int per_lane,
                                float half, float walk, uint32_t seed, float* out, hipStream_t st);
-// Serving: the results of one iteration's ligands, gathered into contiguous staging (one
-// record per ligand, then coordinates and torsion bytes at host-computed offsets).
-struct ResultRec {
-    float score;
-    int32_t k;
-    int32_t tau;
-    int32_t pad;
-    double score64;
-};
-hipError_t launch_gather_results(const int32_t* lig, const int32_t* atom_dst, const int32_t* rot_dst,
-                                 int n, const DockArgs& a, ResultRec* rec, float* coords,
-                                 uint8_t* theta, hipStream_t st);
 // Unfolding of `n_lig` packed ligands in place (ref, ref64), S turns per bond, `passes` passes;
 // turns [passes * R] receives the kept turns (or null).
 hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
@@ -241,6 +249,10 @@ hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
 // Second-stage rescoring of the ranked poses of `n_lig` ligands, one wave per ligand.
 hipError_t launch_rescore2(const DockArgs& a, int n_lig, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+// dst[0..n) = src[0..n), zero[0..nz) = 0 and slot[src[lig + j]] = j for j < n_lig, one kernel;
+// src may be mapped host memory (a kernel reads it over the bus, so no copy call is queued).
+hipError_t launch_stage_ints(const int32_t* src, int32_t* dst, int n, int* zero, int nz, int lig,
+                             int n_lig, int32_t* slot, hipStream_t st);
 // *flag |= 1 if a texel is not finite, |= 2 if one overflows the 16-bit storage (storage 1, 2).
 hipError_t launch_check_texels(const float* v, int64_t count, int storage, int* flag, hipStream_t st);
 // K orientation matrices [K][9] (row-major), FP32 and (unless r64 is null) FP64.

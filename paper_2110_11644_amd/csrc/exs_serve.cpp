@@ -14,7 +14,9 @@
 //    not-yet-docked ligands of the in-flight requests (oldest request first,
 //    capped per iteration), in the work queues of a persistent launch; up to two
 //    iterations run at once on two streams, so a new iteration fills the CUs
-//    the previous one's tail leaves idle;
+//    the previous one's tail leaves idle (the upload stream and the iteration
+//    streams each have a hardware queue of their own, so that neither uploads
+//    nor the next iteration wait behind a running kernel);
 //  * completion: a request whose last ligand finished has its results copied
 //    to host buffers and its arena ranges freed.
 // A ligand's result does not depend on what it is batched with (every lane
@@ -98,6 +100,17 @@ class RangeAlloc {
 
 enum ReqState { kQueued, kInflight, kDone };
 
+// A stream on a hardware queue of its own.  The runtime maps ordinary streams onto a small pool
+// of hardware queues, so two streams can share one, and then a copy or kernel on one waits for
+// every kernel queued before it on the other (a pageable upload even holds the calling thread
+// until then).  A stream created with a CU mask always gets a queue of its own; the mask here
+// holds every CU, so nothing is restricted.  Such a stream synchronizes with the null stream.
+hipError_t own_queue_stream(int cus, hipStream_t* s) {
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    for (int c = 0; c < cus; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+    return hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data());
+}
+
 struct Request {
     int64_t id = 0;
     int L = 0, A = 0, R = 0;
@@ -124,17 +137,21 @@ struct Request {
 struct Iteration {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    // index upload (pinned host, device): processing order [n], queue bounds [kMaxWorkQueues + 1],
-    // then per work-list ligand j: arena ligand [n], staging atom offset [n], staging bond offset [n]
+    // work list indices: processing order [n], queue bounds [kMaxWorkQueues + 1], then per
+    // work-list ligand j: arena ligand [n], result atom offset [n], result bond offset [n].
+    // Written by the host into mapped pinned memory (h_order, hd_order its device address)
+    // and staged into d_order by a kernel: no copy call is queued (the runtime performs small
+    // copies on the host after waiting for the stream's earlier work, which would hold the
+    // scheduler until the running iteration ends).
     int32_t* d_order = nullptr;
     int32_t* h_order = nullptr;
+    int32_t* hd_order = nullptr;
     int* d_counter = nullptr;
     float* scratch = nullptr;
-    // result staging: device, and its pinned host copy (records | coordinates | torsion bytes)
-    ResultRec* d_rec = nullptr;
-    float* d_coords = nullptr;
-    uint8_t* d_theta = nullptr;
+    // results (records | coordinates | torsion bytes), written by each ligand's finish in the
+    // search kernel straight into mapped pinned memory (h_res; hd_res its device address)
     unsigned char* h_res = nullptr;
+    unsigned char* hd_res = nullptr;
     bool running = false;
     struct Work { Request* r; int start, count; };   // ligands start .. start+count-1 of r
     std::vector<Work> work;
@@ -176,6 +193,7 @@ class Server {
     int64_t admitted_bytes_ = 0, peak_admitted_bytes_ = 0, peak_queued_ = 0;
     hipStream_t up_stream_ = nullptr;
     hipEvent_t up_event_ = nullptr;
+    int32_t* res_slot_ = nullptr;   // device [arena ligands]: position in its iteration's work list
     bool up_pending_ = false;
     Iteration it_[2];
 
@@ -255,7 +273,7 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     res_coord_bytes_ = sizeof(float) * 3 * (size_t)EXS_MAX_ATOMS * max_iter_;
     res_theta_bytes_ = (size_t)EXS_MAX_ROT * max_iter_;
     const int64_t scratch_bytes = (int64_t)n_iters_ * resident_ * slot_floats * 4 +
-                                  (int64_t)n_iters_ * (res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_);
+                                  (int64_t)n_iters_ * (4 * (int64_t)max_iter_ + kMaxWorkQueues + 1) * 4;
     per_lig_ = 32 + 12LL * K_ + 40 + 28LL * top_k_ + 4;   // info, per-orientation, best, top-k, order
     per_atom_ = 16 + 24 + 16 + 12;
     per_rot_ = 4 + 16 + K_ + 1 + top_k_;
@@ -297,7 +315,7 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     if ((rc = dev_alloc(dev_bufs_, &info, capL)) || (rc = dev_alloc(dev_bufs_, &ref, capA)) ||
         (rc = dev_alloc(dev_bufs_, &ref64, (size_t)capA * 3)) || (rc = dev_alloc(dev_bufs_, &excl, capA)) ||
         (rc = dev_alloc(dev_bufs_, &ruv, capR)) || (rc = dev_alloc(dev_bufs_, &rmask, capR)) ||
-        (rc = dev_alloc(dev_bufs_, &dg, grids.size())) ||
+        (rc = dev_alloc(dev_bufs_, &dg, grids.size())) || (rc = dev_alloc(dev_bufs_, &res_slot_, capL)) ||
         (rc = dev_alloc(dev_bufs_, &a.orient_score, (size_t)capL * K_)) ||
         (rc = dev_alloc(dev_bufs_, &a.orient_theta, (size_t)capR * K_)) ||
         (rc = dev_alloc(dev_bufs_, &a.orient_tau, (size_t)capL * K_)) ||
@@ -323,23 +341,23 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     a.n_max = EXS_MAX_ATOMS;
     a.slot_floats = slot_floats;
     a.persistent = 1;
-    SRV_TRY(hipStreamCreateWithFlags(&up_stream_, hipStreamNonBlocking));
+    SRV_TRY(own_queue_stream(rt::device_cus(dev_), &up_stream_));
     SRV_TRY(hipEventCreateWithFlags(&up_event_, hipEventDisableTiming));
     for (int i = 0; i < n_iters_; ++i) {
         Iteration& it = it_[i];
-        SRV_TRY(hipStreamCreateWithFlags(&it.stream, hipStreamNonBlocking));
+        SRV_TRY(own_queue_stream(rt::device_cus(dev_), &it.stream));
         SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
         if ((rc = dev_alloc(dev_bufs_, &it.d_order, 4 * (size_t)max_iter_ + kMaxWorkQueues + 1)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_counter, kMaxWorkQueues)) ||
-            (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)) ||
-            (rc = dev_alloc(dev_bufs_, &it.d_rec, (size_t)max_iter_)) ||
-            (rc = dev_alloc(dev_bufs_, &it.d_coords, (size_t)3 * EXS_MAX_ATOMS * max_iter_)) ||
-            (rc = dev_alloc(dev_bufs_, &it.d_theta, (size_t)EXS_MAX_ROT * max_iter_)))
+            (rc = dev_alloc(dev_bufs_, &it.scratch, (size_t)resident_ * slot_floats)))
             return rc;
+        // mapped, coherent pinned memory: kernels read and write it over the bus, uncached
         SRV_TRY(hipHostMalloc((void**)&it.h_order, sizeof(int32_t) * (4 * (size_t)max_iter_ + kMaxWorkQueues + 1),
-                              hipHostMallocDefault));
+                              hipHostMallocMapped | hipHostMallocCoherent));
         SRV_TRY(hipHostMalloc((void**)&it.h_res, res_rec_bytes_ + res_coord_bytes_ + res_theta_bytes_,
-                              hipHostMallocDefault));
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        SRV_TRY(hipHostGetDevicePointer((void**)&it.hd_order, it.h_order, 0));
+        SRV_TRY(hipHostGetDevicePointer((void**)&it.hd_res, it.h_res, 0));
     }
     pocket_ids_.assign(pockets, pockets + n_pockets);
     for (int32_t id : pocket_ids_) rt::pocket_use(id, +1);
@@ -518,23 +536,19 @@ bool Server::launch(Iteration& it) {
     a.queue_bounds = d_bounds;
     a.n_queues = plan.n_queues;
     a.scratch = it.scratch;
-    hipError_t e = hipMemcpyAsync(it.d_order, it.h_order, sizeof(int32_t) * (4 * (size_t)n + kMaxWorkQueues + 1),
-                                  hipMemcpyHostToDevice, it.stream);
-    if (e == hipSuccess) e = launch_zero_ints(it.d_counter, plan.n_queues, it.stream);
+    // each ligand's finish writes its result straight into the pinned result buffer, so the
+    // iteration ends with its search (a kernel queued after it would wait for CUs behind the
+    // other iteration's persistent launch)
+    a.res_slot = res_slot_;
+    a.res_adst = d_lig + n;
+    a.res_rdst = d_lig + 2 * n;
+    a.res_rec = reinterpret_cast<ResultRec*>(it.hd_res);
+    a.res_coords = reinterpret_cast<float*>(it.hd_res + res_rec_bytes_);
+    a.res_theta = it.hd_res + res_rec_bytes_ + res_coord_bytes_;
+    hipError_t e = launch_stage_ints(it.hd_order, it.d_order, 4 * n + kMaxWorkQueues + 1, it.d_counter,
+                                     plan.n_queues, n + kMaxWorkQueues + 1, n, res_slot_, it.stream);
     if (e == hipSuccess)
         e = launch_dock(a, storage_, ppl_, std::min(resident_, a.n_tiles), threads_, lds_, it.stream);
-    // results of this work list into staging, then one copy per staging region to pinned memory
-    if (e == hipSuccess)
-        e = launch_gather_results(d_lig, d_lig + n, d_lig + 2 * n, n, a, it.d_rec, it.d_coords,
-                                  it.d_theta, it.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(it.h_res, it.d_rec, sizeof(ResultRec) * n, hipMemcpyDeviceToHost, it.stream);
-    if (e == hipSuccess && atoms > 0)
-        e = hipMemcpyAsync(it.h_res + res_rec_bytes_, it.d_coords, sizeof(float) * 3 * atoms,
-                           hipMemcpyDeviceToHost, it.stream);
-    if (e == hipSuccess && rots > 0)
-        e = hipMemcpyAsync(it.h_res + res_rec_bytes_ + res_coord_bytes_, it.d_theta, rots,
-                           hipMemcpyDeviceToHost, it.stream);
     if (e == hipSuccess) e = hipEventRecord(it.done, it.stream);
     if (e != hipSuccess) {
         thread_error_ = hipGetErrorString(e);
