@@ -72,6 +72,16 @@ void gather_chunk(const exs_ligand_batch& lib, const int32_t* ids, int n, Chunk&
     }
 }
 
+// Joins the threads it holds when it goes out of scope, so that an exception never leaves a
+// joinable std::thread behind (which would terminate the process).
+struct Joiner {
+    std::vector<std::thread> ts;
+    ~Joiner() {
+        for (auto& t : ts)
+            if (t.joinable()) t.join();
+    }
+};
+
 }  // namespace
 
 extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
@@ -106,7 +116,16 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
         int64_t server = 0;
         int create_rc = EXS_OK;
         std::string create_err;
-        std::thread creator([&] {
+        // a server created here is destroyed on every way out below (after the thread that
+        // creates it has been joined: the guards go out of scope in reverse order)
+        struct ServerGuard {
+            int64_t* s;
+            ~ServerGuard() {
+                if (*s) (void)exs_server_destroy(*s);
+            }
+        } server_guard{&server};
+        Joiner creator;
+        creator.ts.emplace_back([&] {
             create_rc = exs_server_create(pocket_ids, n_pockets, params, &cfg->server, &server);
             if (create_rc != EXS_OK) create_err = exs_last_error();
         });
@@ -149,18 +168,14 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             };
             // every host thread: nothing docks until this pass is done
             const int nth = std::max<int>(packers, std::min<int>(32, (int)std::thread::hardware_concurrency()));
-            std::vector<std::thread> pool;
-            for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+            Joiner pool;
+            for (int t = 1; t < nth; ++t) pool.ts.emplace_back(work);
             work();
-            for (auto& t : pool) t.join();
         }
         const auto t_pre = std::chrono::steady_clock::now();
-        creator.join();
+        creator.ts[0].join();
         for (int l = 0; l < L; ++l)
-            if (rc_of[l]) {
-                if (create_rc == EXS_OK) (void)exs_server_destroy(server);
-                return rt::fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
-            }
+            if (rc_of[l]) return rt::fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
         if (create_rc != EXS_OK) return rt::fail(create_rc, "%s", create_err.c_str());
         // most costly first; chunks cut from that order
         std::vector<int32_t> order(L);
@@ -194,8 +209,8 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
                 cv.notify_all();
             }
         };
-        std::vector<std::thread> threads;
-        for (int t = 0; t < packers; ++t) threads.emplace_back(packer);
+        Joiner threads;
+        for (int t = 0; t < packers; ++t) threads.ts.emplace_back(packer);
         std::vector<float> best(L, INFINITY);
         std::vector<float> part;
         int status = EXS_OK;
@@ -221,11 +236,12 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             for (size_t t = 0; t < ch.ids.size(); ++t) best[ch.ids[t]] = part[t];
             chunks[c] = Chunk();   // the server holds its own copy since the submit
         }
-        for (auto& t : threads) t.join();
+        for (auto& t : threads.ts) t.join();
         exs_server_stats ss;
         memset(&ss, 0, sizeof ss);
         (void)exs_server_get_stats(server, &ss);
         (void)exs_server_destroy(server);
+        server = 0;
         if (status != EXS_OK) return rt::fail(status, "campaign: %s", msg.c_str());
         // hit list: the best round(L * frac) ligands (at least one), score then index ascending
         const int n_hits = L == 0 ? 0 : std::max(1, std::min(L, (int)llround((double)L * frac)));

@@ -105,10 +105,14 @@ enum ReqState { kQueued, kInflight, kDone };
 // every kernel queued before it on the other (a pageable upload even holds the calling thread
 // until then).  A stream created with a CU mask always gets a queue of its own; the mask here
 // holds every CU, so nothing is restricted.  Such a stream synchronizes with the null stream.
+// Where the runtime refuses a CU mask, an ordinary non-blocking stream is used (correct, but
+// iterations may then wait for each other).
 hipError_t own_queue_stream(int cus, hipStream_t* s) {
     std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
     for (int c = 0; c < cus; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
-    return hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data());
+    if (hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data()) == hipSuccess) return hipSuccess;
+    (void)hipGetLastError();
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
 }
 
 struct Request {
