@@ -152,6 +152,7 @@ struct Batch {
     GridDesc* d_grids = nullptr;
     int32_t* d_upload_order = nullptr;   // pocket by pocket, longest first (no-allocation launches)
     uint32_t* d_rot_ac = nullptr;        // [R] dihedral neighbours a | c << 16 of each rotatable bond
+    void* d_block = nullptr;             // the one allocation the arrays above are carved from
     std::mutex order_mu;
     std::map<std::vector<int>, int32_t*> d_orders;   // (S, P, T, persistent, K) -> order array
     std::map<std::vector<int>, std::vector<int>> group_sizes;
@@ -194,18 +195,9 @@ std::shared_ptr<Job> find_job(int64_t id) {
     return it == g_jobs.end() ? nullptr : it->second;
 }
 
-template <class T>
-int dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
-    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    HIP_TRY(hipMalloc((void**)dst, bytes));
-    if (count) HIP_TRY(hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
-    return EXS_OK;
-}
-
 void free_batch(Batch* b) {
-    void* ptrs[] = {b->d_info, b->d_ref, b->d_ref64, b->d_excl, b->d_rot_uv, b->d_rot_mask,
-                    b->d_grids, b->d_upload_order, b->d_rot_ac};
-    for (void* p : ptrs) if (p) (void)hipFree(p);
+    if (b->d_block) (void)hipFree(b->d_block);
+    b->d_block = nullptr;
     for (auto& kv : b->d_orders) (void)hipFree(kv.second);
     b->d_orders.clear();
     for (auto& kv : b->plans) {
@@ -416,88 +408,112 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
         if (L > 0 && in->bond_offset[L] > 0 && !in->bond_ij) return fail(EXS_EINVAL, "null bond_ij");
         if (R > 0 && !in->rot_bond) return fail(EXS_EINVAL, "null rot_bond");
         b->A = A; b->R = R;
-        // pack on host threads
-        std::vector<PackedLigand> packed(L);
+        // The device arrays live in one allocation, filled by one copy from a host block of the
+        // same layout (regions 256-byte aligned): order [L + kMaxWorkQueues + 1], info [L],
+        // ref [A], ref64 [3A], excl [A], rot_uv [R], rot_ac [R], rot_mask [R], grids [slots].
+        size_t off = 0;
+        auto region = [&off](size_t bytes) {
+            const size_t at = off;
+            off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+            return at;
+        };
+        const size_t o_order = region(sizeof(int32_t) * ((size_t)L + kMaxWorkQueues + 1));
+        const size_t o_info = region(sizeof(LigInfo) * (size_t)L);
+        const size_t o_ref = region(sizeof(float4) * (size_t)A);
+        const size_t o_ref64 = region(sizeof(double) * 3 * (size_t)A);
+        const size_t o_excl = region(sizeof(uint4) * (size_t)A);
+        const size_t o_ruv = region(sizeof(uint32_t) * (size_t)R);
+        const size_t o_rac = region(sizeof(uint32_t) * (size_t)R);
+        const size_t o_rmask = region(sizeof(uint4) * (size_t)R);
+        const size_t o_grids = region(sizeof(GridDesc) * pk.size());
+        const size_t total = off;
+        std::unique_ptr<unsigned char[]> host(new unsigned char[total]);   // every byte read is written
+        unsigned char* hb = host.get();
+        LigInfo* h_info = reinterpret_cast<LigInfo*>(hb + o_info);
+        float4* ref = reinterpret_cast<float4*>(hb + o_ref);
+        double* ref64 = reinterpret_cast<double*>(hb + o_ref64);
+        uint4* excl = reinterpret_cast<uint4*>(hb + o_excl);
+        uint32_t* ruv = reinterpret_cast<uint32_t*>(hb + o_ruv);
+        uint32_t* rot_ac = reinterpret_cast<uint32_t*>(hb + o_rac);
+        uint4* rmask = reinterpret_cast<uint4*>(hb + o_rmask);
+        b->info.resize(L);
+        b->mcount.resize(L);
+        b->rot_base.resize(L);
+        // validate, pack and flatten on host threads, each ligand into its own ranges
         std::vector<int> rc_of(L, EXS_OK);
         std::vector<std::string> err_of(L);
         unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         if (L < 256) nth = 1;
-        std::vector<std::thread> pool;
         std::atomic<int> next{0};
         auto work = [&]() {
+            PackedLigand p;   // reused across this thread's ligands (keeps its capacity)
             for (;;) {
-                int l = next.fetch_add(1);
+                const int l = next.fetch_add(1);
                 if (l >= L) break;
-                int a0 = in->atom_offset[l], n = in->atom_offset[l + 1] - a0;
-                int b0 = in->bond_offset[l], nb = in->bond_offset[l + 1] - b0;
-                int r0 = in->rot_offset[l], nr = in->rot_offset[l + 1] - r0;
-                rc_of[l] = pack_ligand(n, in->bond_ij + 2 * (size_t)b0, nb, in->rot_bond + r0, nr,
+                const int a0 = in->atom_offset[l], n = in->atom_offset[l + 1] - a0;
+                const int b0 = in->bond_offset[l], nbl = in->bond_offset[l + 1] - b0;
+                const int r0 = in->rot_offset[l], nr = in->rot_offset[l + 1] - r0;
+                rc_of[l] = pack_ligand(n, in->bond_ij + 2 * (size_t)b0, nbl, in->rot_bond + r0, nr,
                                        in->type + a0, pk[lig_slot[l]]->channels, in->x + a0,
-                                       in->y + a0, in->z + a0, &packed[l], &err_of[l]);
+                                       in->y + a0, in->z + a0, &p, &err_of[l]);
+                if (rc_of[l]) continue;
+                LigInfo& inf = b->info[l];
+                memset(&inf, 0, sizeof inf);
+                inf.atom_base = a0; inf.rot_base = r0; inf.n = (int16_t)p.n; inf.nrot = (int16_t)p.nrot;
+                inf.pocket = (int16_t)lig_slot[l];
+                h_info[l] = inf;
+                b->rot_base[l] = r0;
+                for (int i = 0; i < p.n; ++i) {
+                    const double dx = (double)in->x[a0 + i] - p.centroid[0];
+                    const double dy = (double)in->y[a0 + i] - p.centroid[1];
+                    const double dz = (double)in->z[a0 + i] - p.centroid[2];
+                    const int t = in->type[a0 + i];
+                    ref[a0 + i] = make_float4((float)dx, (float)dy, (float)dz, __builtin_bit_cast(float, t));
+                    ref64[(size_t)(a0 + i) * 3 + 0] = dx;
+                    ref64[(size_t)(a0 + i) * 3 + 1] = dy;
+                    ref64[(size_t)(a0 + i) * 3 + 2] = dz;
+                    excl[a0 + i] = p.excl[i].as_uint4();
+                }
+                b->mcount[l].resize(p.nrot);
+                for (int r = 0; r < p.nrot; ++r) {
+                    // lowest-index neighbours of u (other than v) and of v (other than u): the
+                    // dihedral of the bond in the second-stage score
+                    const int u = p.rot_u[r], v = p.rot_v[r];
+                    int na = 0xffff, nc = 0xffff;
+                    for (int e = 0; e < nbl; ++e) {
+                        const int bi = in->bond_ij[2 * (size_t)(b0 + e)], bj = in->bond_ij[2 * (size_t)(b0 + e) + 1];
+                        if (bi == u && bj != v) na = std::min(na, bj);
+                        if (bj == u && bi != v) na = std::min(na, bi);
+                        if (bi == v && bj != u) nc = std::min(nc, bj);
+                        if (bj == v && bi != u) nc = std::min(nc, bi);
+                    }
+                    rot_ac[r0 + r] = (uint32_t)na | ((uint32_t)nc << 16);
+                    ruv[r0 + r] = (uint32_t)p.rot_u[r] | ((uint32_t)p.rot_v[r] << 16);
+                    rmask[r0 + r] = p.moving[r].as_uint4();
+                    b->mcount[l][r] = (int16_t)p.moving[r].count();
+                }
             }
         };
-        for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work);
-        work();
-        for (auto& t : pool) t.join();
+        {
+            std::vector<std::thread> pool;
+            try {
+                for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work);
+            } catch (...) {   // fewer threads: the ones started and this one finish the work
+            }
+            work();
+            for (auto& t : pool) t.join();
+        }
         for (int l = 0; l < L; ++l)
             if (rc_of[l]) return fail(rc_of[l], "ligand %d: %s", l, err_of[l].c_str());
-        // flatten
-        std::vector<float4> ref(A);
-        std::vector<double> ref64((size_t)A * 3);
-        std::vector<uint4> excl(A);
-        std::vector<uint32_t> ruv(R), rot_ac(R);
-        std::vector<uint4> rmask(R);
-        b->info.resize(L);
-        b->mcount.resize(L);
-        b->rot_base.resize(L);
-        for (int l = 0; l < L; ++l) {
-            const PackedLigand& p = packed[l];
-            int a0 = in->atom_offset[l], r0 = in->rot_offset[l];
-            LigInfo& inf = b->info[l];
-            memset(&inf, 0, sizeof inf);
-            inf.atom_base = a0; inf.rot_base = r0; inf.n = (int16_t)p.n; inf.nrot = (int16_t)p.nrot;
-            inf.pocket = (int16_t)lig_slot[l];
-            b->n_max = std::max(b->n_max, p.n);
-            b->rot_base[l] = r0;
-            for (int i = 0; i < p.n; ++i) {
-                double dx = (double)in->x[a0 + i] - p.centroid[0];
-                double dy = (double)in->y[a0 + i] - p.centroid[1];
-                double dz = (double)in->z[a0 + i] - p.centroid[2];
-                int t = in->type[a0 + i];
-                ref[a0 + i] = make_float4((float)dx, (float)dy, (float)dz, __builtin_bit_cast(float, t));
-                ref64[(size_t)(a0 + i) * 3 + 0] = dx;
-                ref64[(size_t)(a0 + i) * 3 + 1] = dy;
-                ref64[(size_t)(a0 + i) * 3 + 2] = dz;
-                excl[a0 + i] = p.excl[i].as_uint4();
-            }
-            b->mcount[l].resize(p.nrot);
-            const int b0 = in->bond_offset[l], nbl = in->bond_offset[l + 1] - b0;
-            for (int r = 0; r < p.nrot; ++r) {
-                // lowest-index neighbours of u (other than v) and of v (other than u): the
-                // dihedral of the bond in the second-stage score
-                const int u = p.rot_u[r], v = p.rot_v[r];
-                int na = 0xffff, nc = 0xffff;
-                for (int e = 0; e < nbl; ++e) {
-                    const int bi = in->bond_ij[2 * (size_t)(b0 + e)], bj = in->bond_ij[2 * (size_t)(b0 + e) + 1];
-                    if (bi == u && bj != v) na = std::min(na, bj);
-                    if (bj == u && bi != v) na = std::min(na, bi);
-                    if (bi == v && bj != u) nc = std::min(nc, bj);
-                    if (bj == v && bi != u) nc = std::min(nc, bi);
-                }
-                rot_ac[r0 + r] = (uint32_t)na | ((uint32_t)nc << 16);
-                ruv[r0 + r] = (uint32_t)p.rot_u[r] | ((uint32_t)p.rot_v[r] << 16);
-                rmask[r0 + r] = p.moving[r].as_uint4();
-                b->mcount[l][r] = (int16_t)p.moving[r].count();
-            }
-        }
-        std::vector<GridDesc> grids(pk.size());
-        for (size_t s = 0; s < pk.size(); ++s) {
-            grids[s] = pk[s]->desc;
-            b->storage_of_slot.push_back(pk[s]->storage);
+        for (int l = 0; l < L; ++l) b->n_max = std::max<int>(b->n_max, b->info[l].n);
+        GridDesc* h_grids = reinterpret_cast<GridDesc*>(hb + o_grids);
+        for (size_t sl = 0; sl < pk.size(); ++sl) {
+            h_grids[sl] = pk[sl]->desc;
+            b->storage_of_slot.push_back(pk[sl]->storage);
         }
         // one work queue, pocket by pocket and longest first within a pocket, by the cost at the
         // full search settings (the order of launches that cannot build one of their own)
-        std::vector<int32_t> up_order((size_t)L + kMaxWorkQueues + 1);
+        int32_t* up_order = reinterpret_cast<int32_t*>(hb + o_order);
         {
             std::vector<double> cost(L);
             std::vector<int> pocket(L);
@@ -505,21 +521,44 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
                 cost[l] = ligand_cost(b->info[l].n, b->mcount[l].data(), b->info[l].nrot, 1, 32, 2, 27);
                 pocket[l] = b->info[l].pocket;
             }
-            work_queues(L, pocket.data(), cost.data(), 1, true, up_order.data(), up_order.data() + L);
+            work_queues(L, pocket.data(), cost.data(), 1, true, up_order, up_order + L);
         }
         hipStream_t st = (hipStream_t)stream;
-        int rc;
-        if ((rc = dev_upload(&b->d_upload_order, up_order.data(), (size_t)L, st)) ||
-            (rc = dev_upload(&b->d_info, b->info.data(), (size_t)L, st)) ||
-            (rc = dev_upload(&b->d_ref, ref.data(), (size_t)A, st)) ||
-            (rc = dev_upload(&b->d_ref64, ref64.data(), (size_t)A * 3, st)) ||
-            (rc = dev_upload(&b->d_excl, excl.data(), (size_t)A, st)) ||
-            (rc = dev_upload(&b->d_rot_uv, ruv.data(), (size_t)R, st)) ||
-            (rc = dev_upload(&b->d_rot_ac, rot_ac.data(), (size_t)R, st)) ||
-            (rc = dev_upload(&b->d_rot_mask, rmask.data(), (size_t)R, st)) ||
-            (rc = dev_upload(&b->d_grids, grids.data(), grids.size(), st))) {
-            free_batch(b.get());
-            return rc;
+        {
+            hipError_t e = hipMalloc(&b->d_block, total);
+            if (e != hipSuccess) {
+                b->d_block = nullptr;
+                (void)hipGetLastError();
+                return fail(EXS_ENOMEM, "device allocation of %zu B for the ligand batch: %s", total,
+                            hipGetErrorString(e));
+            }
+            unsigned char* d = static_cast<unsigned char*>(b->d_block);
+            b->d_upload_order = reinterpret_cast<int32_t*>(d + o_order);
+            b->d_info = reinterpret_cast<LigInfo*>(d + o_info);
+            b->d_ref = reinterpret_cast<float4*>(d + o_ref);
+            b->d_ref64 = reinterpret_cast<double*>(d + o_ref64);
+            b->d_excl = reinterpret_cast<uint4*>(d + o_excl);
+            b->d_rot_uv = reinterpret_cast<uint32_t*>(d + o_ruv);
+            b->d_rot_ac = reinterpret_cast<uint32_t*>(d + o_rac);
+            b->d_rot_mask = reinterpret_cast<uint4*>(d + o_rmask);
+            b->d_grids = reinterpret_cast<GridDesc*>(d + o_grids);
+            // one copy of the whole block (the padding between regions is zeroed first)
+            const std::pair<size_t, size_t> used[] = {
+                {o_order, sizeof(int32_t) * ((size_t)L + kMaxWorkQueues + 1)},
+                {o_info, sizeof(LigInfo) * (size_t)L}, {o_ref, sizeof(float4) * (size_t)A},
+                {o_ref64, sizeof(double) * 3 * (size_t)A}, {o_excl, sizeof(uint4) * (size_t)A},
+                {o_ruv, sizeof(uint32_t) * (size_t)R}, {o_rac, sizeof(uint32_t) * (size_t)R},
+                {o_rmask, sizeof(uint4) * (size_t)R}, {o_grids, sizeof(GridDesc) * pk.size()}};
+            for (size_t i = 0; i < sizeof used / sizeof used[0]; ++i) {
+                const size_t end = used[i].first + used[i].second;
+                const size_t next_at = i + 1 < sizeof used / sizeof used[0] ? used[i + 1].first : total;
+                memset(hb + end, 0, next_at - end);
+            }
+            e = hipMemcpyAsync(d, hb, total, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) {
+                free_batch(b.get());
+                return fail(EXS_EDEVICE, "upload: %s", hipGetErrorString(e));
+            }
         }
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
