@@ -416,11 +416,11 @@ int exs_server_destroy(int64_t server);
  * writer joined by queues, which keeps the GPUs fed while the host prepares ligands (Sec. 3.2,
  * several workers per GPU in Sec. 4.3).  exs_campaign_run does that on one device for a library
  * in host memory: it validates every ligand and computes its search cost on the host's
- * threads, cuts the library, most costly ligands first, into chunks of chunk_ligands (the
- * first ones 1,024, 2,048, ... ligands, doubling up to that, so the device starts early), and
- * streams the chunks through a server (exs_server_*, created while the library is validated)
- * configured by `server`: `packers` threads pack and submit chunks while earlier ones dock.  It
- * returns when every ligand is docked.
+ * threads, cuts the library -- pocket by pocket, most costly ligands first within a pocket --
+ * into chunks of chunk_ligands (the first ones 1,024, 2,048, ... ligands, doubling up to that,
+ * so the device starts early), and streams the chunks through a server (exs_server_*, created
+ * while the library is validated) configured by `server`: `packers` threads pack and submit
+ * chunks while earlier ones dock.  It returns when every ligand is docked.
  */
 typedef struct {
     int32_t chunk_ligands;      /* ligands per chunk (0: 16384)                              */
