@@ -149,30 +149,30 @@ hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int n
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st) {
+hipError_t launch_rank(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st) {
     if (n_lig <= 0) return hipSuccess;
     // up to 4 waves (ligands) per block, within 64 KB of LDS
     const size_t per_wave = (size_t)rank_lds_words(a.K) * sizeof(int);
     const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     hipLaunchKernelGGL(rank_kernel, dim3((n_lig + waves - 1) / waves), dim3(waves * kWave),
-                       waves * per_wave, st, a, n_lig);
+                       waves * per_wave, st, a, n_lig, order);
     return hipGetLastError();
 }
 
-hipError_t launch_rescore2(const DockArgs& a, int n_lig, hipStream_t st) {
+hipError_t launch_rescore2(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st) {
     if (n_lig <= 0) return hipSuccess;
     constexpr int kWavesPerBlock = 4;
     const size_t per_wave = sizeof(LigLds) + (size_t)kMaxAtoms * 3 * sizeof(double);
     hipLaunchKernelGGL(rescore2_kernel, dim3((n_lig + kWavesPerBlock - 1) / kWavesPerBlock),
-                       dim3(kWavesPerBlock * kWave), kWavesPerBlock * per_wave, st, a, n_lig);
+                       dim3(kWavesPerBlock * kWave), kWavesPerBlock * per_wave, st, a, n_lig, order);
     return hipGetLastError();
 }
 
 hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
-                         const uint4* rot_mask, int32_t* turns, int n_lig, int R, int S, int passes,
-                         hipStream_t st) {
+                         const uint4* rot_mask, int32_t* turns, const int32_t* order, int n_lig, int R,
+                         int S, int passes, hipStream_t st) {
     if (n_lig <= 0) return hipSuccess;
-    UnfoldArgs a{info, ref, ref64, rot_uv, rot_mask, turns, n_lig, R, passes, 0};
+    UnfoldArgs a{info, ref, ref64, rot_uv, rot_mask, turns, order, n_lig, R, passes, 0};
     constexpr int kWavesPerBlock = 4;
     const dim3 grid((n_lig + kWavesPerBlock - 1) / kWavesPerBlock), block(kWavesPerBlock * kWave);
     const size_t lds = (size_t)kWavesPerBlock * kMaxAtoms * sizeof(float4);

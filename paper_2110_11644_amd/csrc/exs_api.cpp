@@ -776,8 +776,8 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         hipError_t e = launch_zero_ints(a.tile_counter, n_queues, st);
         if (e != hipSuccess) return e;
         e = launch_dock(a, storage, ppl, resident, threads, lds, st);
-        if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, st);
-        if (e == hipSuccess && a.rescore2) e = launch_rescore2(a, b.L, st);
+        if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, d_order, st);
+        if (e == hipSuccess && a.rescore2) e = launch_rescore2(a, b.L, d_order, st);
         return e;
     }
     int start = 0;
@@ -794,8 +794,9 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         start += gsz;
     }
     hipError_t e = hipSuccess;
-    if (base.rank_keep > 0) e = launch_rank(base, b.L, st);
-    if (e == hipSuccess && base.rescore2) e = launch_rescore2(base, b.L, st);
+    // d_order: every pocket's ligands, longest first, one pocket after another
+    if (base.rank_keep > 0) e = launch_rank(base, b.L, d_order, st);
+    if (e == hipSuccess && base.rescore2) e = launch_rescore2(base, b.L, d_order, st);
     return e;
 }
 
@@ -1188,7 +1189,7 @@ int exs_unfold_ligands(int64_t batch, int torsion_steps, int passes, void* strea
         const size_t nt = (size_t)passes * b->R;
         if (turns_out && nt > 0) HIP_TRY(hipMalloc(&d_turns, nt * sizeof(int32_t)));
         hipError_t e = launch_unfold(b->d_info, b->d_ref, b->d_ref64, b->d_rot_uv, b->d_rot_mask,
-                                     d_turns, b->L, b->R, torsion_steps, passes, st);
+                                     d_turns, b->d_upload_order, b->L, b->R, torsion_steps, passes, st);
         if (e == hipSuccess && d_turns)
             e = hipMemcpyAsync(turns_out, d_turns, nt * sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -241,13 +241,15 @@ hipError_t launch_gather_probe(const GridDesc* gd, int storage, int nb, int64_t 
                                float half, float walk, uint32_t seed, float* out, hipStream_t st);
 // Unfolding of `n_lig` packed ligands in place (ref, ref64), S turns per bond, `passes` passes;
 // turns [passes * R] receives the kept turns (or null).
+// The waves take the ligands in `order` (a permutation of 0..n_lig-1, longest first).
 hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const uint32_t* rot_uv,
-                         const uint4* rot_mask, int32_t* turns, int n_lig, int R, int S, int passes,
-                         hipStream_t st);
-// Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand.
-hipError_t launch_rank(const DockArgs& a, int n_lig, hipStream_t st);
-// Second-stage rescoring of the ranked poses of `n_lig` ligands, one wave per ligand.
-hipError_t launch_rescore2(const DockArgs& a, int n_lig, hipStream_t st);
+                         const uint4* rot_mask, int32_t* turns, const int32_t* order, int n_lig, int R,
+                         int S, int passes, hipStream_t st);
+// Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand, the
+// ligands taken in `order` (a permutation of 0..n_lig-1, longest first).
+hipError_t launch_rank(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st);
+// Second-stage rescoring of the ranked poses of `n_lig` ligands, one wave per ligand, in `order`.
+hipError_t launch_rescore2(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 // dst[0..n) = src[0..n), zero[0..nz) = 0 and slot[src[lig + j]] = j for j < n_lig, one kernel;
 // src may be mapped host memory (a kernel reads it over the bus, so no copy call is queued).
