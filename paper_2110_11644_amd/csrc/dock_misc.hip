@@ -152,7 +152,7 @@ hipError_t launch_expand_grid(const float* src, void* dst, int nx, int ny, int n
 hipError_t launch_rank(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st) {
     if (n_lig <= 0) return hipSuccess;
     // up to 4 waves (ligands) per block, within 64 KB of LDS
-    const size_t per_wave = (size_t)rank_lds_words(a.K) * sizeof(int);
+    const size_t per_wave = (size_t)rank_lds_words(a.K, a.n_max) * sizeof(int);
     const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     hipLaunchKernelGGL(rank_kernel, dim3((n_lig + waves - 1) / waves), dim3(waves * kWave),
                        waves * per_wave, st, a, n_lig, order);
@@ -175,7 +175,7 @@ hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const 
     UnfoldArgs a{info, ref, ref64, rot_uv, rot_mask, turns, order, n_lig, R, passes, 0};
     constexpr int kWavesPerBlock = 4;
     const dim3 grid((n_lig + kWavesPerBlock - 1) / kWavesPerBlock), block(kWavesPerBlock * kWave);
-    const size_t lds = (size_t)kWavesPerBlock * kMaxAtoms * sizeof(float4);
+    const size_t lds = (size_t)kWavesPerBlock * kUnfoldLdsPerWave;
     switch (S) {
         case 8: hipLaunchKernelGGL(unfold_kernel<8>, grid, block, lds, st, a); break;
         case 16: hipLaunchKernelGGL(unfold_kernel<16>, grid, block, lds, st, a); break;
