@@ -345,11 +345,31 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     a.n_max = EXS_MAX_ATOMS;
     a.slot_floats = slot_floats;
     a.persistent = 1;
-    SRV_TRY(own_queue_stream(rt::device_cus(dev_), &up_stream_));
+    // the streams get a hardware queue each, several ms apiece: created on threads of their own
+    {
+        hipStream_t* target[3] = {&up_stream_, &it_[0].stream, n_iters_ > 1 ? &it_[1].stream : nullptr};
+        hipError_t err[3] = {hipSuccess, hipSuccess, hipSuccess};
+        const int cus = rt::device_cus(dev_);
+        struct Join {
+            std::vector<std::thread> ts;
+            ~Join() {
+                for (auto& t : ts)
+                    if (t.joinable()) t.join();
+            }
+        } join;
+        for (int i = 1; i < 3; ++i)
+            if (target[i])
+                join.ts.emplace_back([&, i] {
+                    err[i] = hipSetDevice(dev_);
+                    if (err[i] == hipSuccess) err[i] = own_queue_stream(cus, target[i]);
+                });
+        err[0] = own_queue_stream(cus, target[0]);
+        for (auto& t : join.ts) t.join();
+        for (hipError_t e : err) SRV_TRY(e);
+    }
     SRV_TRY(hipEventCreateWithFlags(&up_event_, hipEventDisableTiming));
     for (int i = 0; i < n_iters_; ++i) {
         Iteration& it = it_[i];
-        SRV_TRY(own_queue_stream(rt::device_cus(dev_), &it.stream));
         SRV_TRY(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
         if ((rc = dev_alloc(dev_bufs_, &it.d_order, 4 * (size_t)max_iter_ + kMaxWorkQueues + 1)) ||
             (rc = dev_alloc(dev_bufs_, &it.d_counter, kMaxWorkQueues)) ||
