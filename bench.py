@@ -443,7 +443,9 @@ def run_serving(args, torch, S, B):
     def serve(load):
         """The trace at `load` (arrival times scaled) through a fresh server."""
         scale = args.load / load
-        srv = B.exs_server_create(pids, prm, hbm_budget_bytes=8 << 30)
+        srv = B.exs_server_create(pids, prm, hbm_budget_bytes=8 << 30,
+                                  max_iter_ligands=args.serve_max_iter,
+                                  max_inflight_iters=args.serve_inflight)
         lat, t0, done = replay(
             lambda b: B.exs_server_submit(srv, b, pocket_ids=pids),
             lambda h, b: B.exs_server_poll(srv, h, b.n_ligands, int(b.atom_offset[-1])),
@@ -832,6 +834,10 @@ def main():
                     help="scale/small: unfold the ligands first (passes; 0 = off), timed apart")
     ap.add_argument("--requests", type=int, default=1000, help="serving: timed requests")
     ap.add_argument("--sweep", default="0.5,0.9", help="serving: other offered loads to serve")
+    ap.add_argument("--serve-max-iter", type=int, default=0,
+                    help="serving workload: ligands per server iteration (0 = the server's default)")
+    ap.add_argument("--serve-inflight", type=int, default=0,
+                    help="serving workload: iterations in flight, 1 or 2 (0 = the server's default)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--oracle-sample", type=int, default=192,
                     help="precision: ligands checked against the FP64 oracle")
@@ -853,7 +859,7 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

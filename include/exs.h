@@ -367,7 +367,7 @@ typedef struct {
     int64_t hbm_budget_bytes;   /* device memory for scratch + admitted requests (0: 2 GiB);
                                    clamped to the free device memory (hipMemGetInfo) less a
                                    reserve of max(1 GiB, 5 % of the device) at creation */
-    int32_t max_iter_ligands;   /* ligands per iteration launch (0: two waves of workgroups)  */
+    int32_t max_iter_ligands;   /* ligands per iteration launch (0: four waves of workgroups) */
     int32_t max_inflight_iters; /* 1 or 2 (0: 2)                                             */
     int32_t max_arena_ligands;  /* cap on the arena's ligand slots (0: from the budget)       */
     int32_t pad;
