@@ -161,10 +161,8 @@ hipError_t launch_rank(const DockArgs& a, int n_lig, const int32_t* order, hipSt
 
 hipError_t launch_rescore2(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st) {
     if (n_lig <= 0) return hipSuccess;
-    constexpr int kWavesPerBlock = 4;
-    const size_t per_wave = sizeof(LigLds) + (size_t)kMaxAtoms * 3 * sizeof(double);
-    hipLaunchKernelGGL(rescore2_kernel, dim3((n_lig + kWavesPerBlock - 1) / kWavesPerBlock),
-                       dim3(kWavesPerBlock * kWave), kWavesPerBlock * per_wave, st, a, n_lig, order);
+    hipLaunchKernelGGL(rescore2_kernel, dim3(n_lig), dim3(kRescoreWaves * kWave),
+                       rescore2_lds_bytes(kRescoreWaves), st, a, n_lig, order);
     return hipGetLastError();
 }
 

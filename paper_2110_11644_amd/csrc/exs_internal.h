@@ -249,7 +249,8 @@ hipError_t launch_unfold(const LigInfo* info, float4* ref, double* ref64, const 
 // Ranking of the final poses of `n_lig` ligands (rank_keep > 0), one wave per ligand, the
 // ligands taken in `order` (a permutation of 0..n_lig-1, longest first).
 hipError_t launch_rank(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st);
-// Second-stage rescoring of the ranked poses of `n_lig` ligands, one wave per ligand, in `order`.
+// Second-stage rescoring of the ranked poses of `n_lig` ligands, one block of waves per ligand,
+// the ligands taken in `order`.
 hipError_t launch_rescore2(const DockArgs& a, int n_lig, const int32_t* order, hipStream_t st);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
 // dst[0..n) = src[0..n), zero[0..nz) = 0 and slot[src[lig + j]] = j for j < n_lig, one kernel;

@@ -65,6 +65,8 @@ def test_campaign_hits_match_oracle(B, oracle_lib):
     st = res["stats"]
     log("stats", st)
     assert st["ligands"] == L and st["chunks"] == 7 and st["hits"] == 20
+    # the validation pass and the first submission happen within the call
+    assert 0.0 <= st["prepass_seconds"] <= st["first_submit_seconds"] <= st["seconds"]
     assert np.array_equal(res["best_score"], plain["best_score"])
     # hits: best first, ties to the lower index
     hs = res["best_score"][res["hits"]]
