@@ -450,6 +450,7 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
             for (;;) {
                 const int l = next.fetch_add(1);
                 if (l >= L) break;
+                try {   // an exception must not leave a worker thread (it would end the process)
                 const int a0 = in->atom_offset[l], n = in->atom_offset[l + 1] - a0;
                 const int b0 = in->bond_offset[l], nbl = in->bond_offset[l + 1] - b0;
                 const int r0 = in->rot_offset[l], nr = in->rot_offset[l + 1] - r0;
@@ -491,6 +492,10 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
                     ruv[r0 + r] = (uint32_t)p.rot_u[r] | ((uint32_t)p.rot_v[r] << 16);
                     rmask[r0 + r] = p.moving[r].as_uint4();
                     b->mcount[l][r] = (int16_t)p.moving[r].count();
+                }
+                } catch (const std::exception& ex) {
+                    rc_of[l] = EXS_ENOMEM;
+                    err_of[l] = std::string("exception: ") + ex.what();
                 }
             }
         };

@@ -156,15 +156,20 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
                         err_of[l] = "bad offsets";
                         continue;
                     }
-                    PackedLigand pk;
-                    rc_of[l] = pack_ligand(n, lib.bond_ij + 2 * (size_t)b0, nb, lib.rot_bond + r0, nr,
-                                           lib.type + a0, channels[slot], lib.x + a0, lib.y + a0,
-                                           lib.z + a0, &pk, &err_of[l]);
-                    if (rc_of[l]) continue;
-                    std::vector<int16_t> m(pk.nrot);
-                    for (int b = 0; b < pk.nrot; ++b) m[b] = (int16_t)pk.moving[b].count();
-                    cost[l] = ligand_cost(pk.n, m.data(), pk.nrot, params->n_orient,
-                                          params->torsion_steps, params->passes, params->n_offsets);
+                    try {   // an exception must not leave a worker thread
+                        PackedLigand pk;
+                        rc_of[l] = pack_ligand(n, lib.bond_ij + 2 * (size_t)b0, nb, lib.rot_bond + r0, nr,
+                                               lib.type + a0, channels[slot], lib.x + a0, lib.y + a0,
+                                               lib.z + a0, &pk, &err_of[l]);
+                        if (rc_of[l]) continue;
+                        std::vector<int16_t> m(pk.nrot);
+                        for (int b = 0; b < pk.nrot; ++b) m[b] = (int16_t)pk.moving[b].count();
+                        cost[l] = ligand_cost(pk.n, m.data(), pk.nrot, params->n_orient,
+                                              params->torsion_steps, params->passes, params->n_offsets);
+                    } catch (const std::exception& ex) {
+                        rc_of[l] = EXS_ENOMEM;
+                        err_of[l] = std::string("exception: ") + ex.what();
+                    }
                 }
             };
             // every host thread: nothing docks until this pass is done
@@ -204,10 +209,15 @@ extern "C" int exs_campaign_run(const int32_t* pocket_ids, int n_pockets,
             for (;;) {
                 const int c = next.fetch_add(1);
                 if (c >= n_chunks) return;
-                gather_chunk(lib, order.data() + start[c], start[c + 1] - start[c], chunks[c]);
-                const exs_ligand_batch view = chunks[c].view();
                 int64_t h = 0;
-                const int rc = exs_server_submit(server, &view, &h);
+                int rc;
+                try {   // an exception must not leave a worker thread; the chunk fails instead
+                    gather_chunk(lib, order.data() + start[c], start[c + 1] - start[c], chunks[c]);
+                    const exs_ligand_batch view = chunks[c].view();
+                    rc = exs_server_submit(server, &view, &h);
+                } catch (const std::exception&) {
+                    rc = EXS_ENOMEM;
+                }
                 std::lock_guard<std::mutex> lk(mu);
                 if (c == 0) t_first = std::chrono::steady_clock::now();
                 handle[c] = h;

@@ -388,7 +388,15 @@ int Server::create(const int32_t* pockets, int n_pockets, const exs_search_param
     }
     pocket_ids_.assign(pockets, pockets + n_pockets);
     for (int32_t id : pocket_ids_) rt::pocket_use(id, +1);
-    thread_ = std::thread([this] { loop(); });
+    thread_ = std::thread([this] {
+        try {
+            loop();
+        } catch (const std::exception& e) {   // fail the server (pollers see it) rather than the process
+            std::lock_guard<std::mutex> lk(mu_);
+            thread_error_ = std::string("scheduler: ") + e.what();
+            done_cv_.notify_all();
+        }
+    });
     return EXS_OK;
 }
 
