@@ -323,3 +323,20 @@ def test_byte_budget_holds_requests_back(B, setup):
         finally:
             B.exs_server_destroy(srv)
     assert ei.value.code == B.EXS_ENOMEM
+
+
+def test_overlapping_iterations_equal_one_at_a_time(B, setup):
+    """Small iterations, two in flight on their own hardware queues (the search writes each
+    ligand's result straight into the iteration's pinned buffer), give bit for bit the results
+    of the same requests served one iteration at a time."""
+    pids, reqs = setup
+    log("serving: 12 requests, iterations of 16 ligands, 2 in flight vs 1")
+    two, st2 = serve(B, pids, reqs, max_iter_ligands=16, max_inflight_iters=2)
+    one, st1 = serve(B, pids, reqs, max_iter_ligands=16, max_inflight_iters=1)
+    log("stats", st2, st1)
+    assert st2["iterations"] >= 2 and st1["iterations"] >= 2
+    for i in range(len(reqs)):
+        for key in ("best_score", "coords"):
+            assert np.array_equal(two[i][key], one[i][key]), (i, key)
+        for key in ("orient", "theta", "tau"):
+            assert np.array_equal(two[i]["desc"][key], one[i]["desc"][key]), (i, key)
