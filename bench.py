@@ -721,6 +721,48 @@ def batched_launch(B, torch, pids, batch, s, storage, top_k, steps, warmup, stre
     return batch.n_ligands * steps / dt, kms, dt / steps, out
 
 
+def method_steps_leg(B, torch, S, pid, s, stream, n=3000):
+    """The method's other steps on the first `n` scale ligands (Sec. 3.1): unfolding of the
+    input conformations (S = 32, 2 passes; host wall time of the call), then one dock job as
+    it is and one that also ranks each ligand's final poses (3 A clusters, 30 kept) and rescores
+    the ranked poses with the second-stage score (HIP-event times of the job, median of 3)."""
+    batch = S.make_ligand_batch(S.WORKLOADS["scale"], 0, n)
+    L, A = batch.n_ligands, int(batch.atom_offset[-1])
+    bid = B.exs_upload_ligands(batch, pocket_ids=[pid], stream=stream)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.exs_unfold_ligands(bid, s.torsion_steps, 2, stream=stream)
+        unfold_ms = (time.perf_counter() - t0) * 1e3
+
+        def job_ms(prm, ranked):
+            ms, nc = [], None
+            for _ in range(4):
+                job = B.exs_dock_batch(bid, prm, stream=stream)
+                B.exs_get_best_poses(job, L, A)
+                if ranked:
+                    nc, _ = B.exs_get_ranked_poses(job, L, 30)
+                    B.exs_get_rescored_poses(job, L, 30)
+                ms.append(B.exs_job_elapsed_ms(job))
+                B.exs_release_job(job)
+            return float(np.median(ms[1:])), nc
+
+        plain = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                                s.clash_cutoff, s.clash_penalty)
+        ranked = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
+                                 s.clash_cutoff, s.clash_penalty, flags=B.EXS_FLAG_RESCORE2,
+                                 cluster_rmsd_A=3.0, rank_keep=30)
+        dock_ms, _ = job_ms(plain, False)
+        full_ms, nc = job_ms(ranked, True)
+    finally:
+        B.exs_release_ligands(bid)
+    return {"ligands": L, "unfold_ms": round(unfold_ms, 3), "dock_ms": round(dock_ms, 3),
+            "dock_rank_rescore2_ms": round(full_ms, 3),
+            "rank_rescore2_ms": round(full_ms - dock_ms, 3),
+            "clusters_mean": round(float(nc.mean()), 2),
+            "steps": "unfold (S=32, 2 passes), dock, rank (3 A, keep 30), second-stage rescoring"}
+
+
 def driver_legs(args, torch, S, B):
     """The rest of the headline metric, under the same run: the batched workload (100,000
     ligands over 15 resident pockets) as one persistent launch in a hipGraph, FP32 and with
@@ -974,6 +1016,11 @@ def main():
         cpu = cpu_baseline(wl.name, pocket, batch, s)
 
     B.exs_release_ligands(bid)
+    method_steps = None
+    if args.workload == "scale" and not args.no_extra and args.ligands is None and storage == 0:
+        progress("method steps: unfold, dock, rank, rescore (3,000 ligands)")
+        method_steps = method_steps_leg(B, torch, S, pid, s, stream)
+        progress("method steps: %s" % method_steps)
     B.exs_unload_pocket(pid)
     extra = None
     if args.workload == "scale" and not args.no_extra and args.ligands is None:
@@ -1012,6 +1059,8 @@ def main():
         # identifies the results (runs with equal results print the same digest)
         "best_scores_sha256": __import__("hashlib").sha256(out["best_score"].tobytes()).hexdigest()[:16],
     }
+    if method_steps is not None:
+        line["method_steps"] = method_steps
     if extra is not None:
         legs = extra["legs"]
         line["batched"] = extra
