@@ -536,7 +536,8 @@ bool Server::launch(Iteration& it) {
         r->scheduled += take;
     }
     if (lig.empty()) return false;
-    // work queues (queue_plan: spread or pocket-major), then the gather's indices
+    // work queues (queue_plan: spread or pocket-major), then each ligand's arena index and the
+    // offsets of its coordinates and torsion bytes in the result buffer
     const int n = (int)lig.size();
     int32_t* h_ord = it.h_order;
     int32_t* h_bounds = h_ord + n;
