@@ -65,7 +65,8 @@ const char* exs_last_error(void);
  *   values      [channels][nz][ny][nx] FP32 texels, x fastest; one channel per
  *               ligand atom type.  Host pointer, or device pointer when
  *               values_on_device = 1.  Copied; the caller keeps ownership.
- *   nx, ny, nz  texels per axis, each >= 2.
+ *   nx, ny, nz  texels per axis, each >= 2; nx * ny and nz below 2^23 (the search
+ *               forms cell offsets with 24-bit multiplies).
  *   spacing_A   texel spacing (A), > 0.  Texel (i,j,k) sits at
  *               origin_A + spacing_A * (i,j,k); the pocket centre is the grid
  *               centre, where each ligand's centroid is placed.
@@ -78,8 +79,9 @@ const char* exs_last_error(void);
  *               copy must stay below 2 GiB.  The FP32 master copy is always
  *               kept as well: it feeds the FP64 rescoring of the top poses.
  *   pocket_id_out  receives the handle.
- * Errors: EXS_EINVAL (bad sizes, channels > EXS_MAX_CHANNELS, non-finite
- * texels, an expanded channel of 2 GiB or more), EXS_ENOMEM, EXS_EDEVICE.
+ * Errors: EXS_EINVAL (bad sizes, nx * ny or nz of 2^23 or more, channels >
+ * EXS_MAX_CHANNELS, non-finite texels, an expanded channel of 2 GiB or more),
+ * EXS_ENOMEM, EXS_EDEVICE.
  */
 int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channels,
                          double spacing_A, const double origin_A[3], int storage,

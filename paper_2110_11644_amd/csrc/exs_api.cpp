@@ -269,6 +269,9 @@ int exs_load_pocket_grid(const float* values, int nx, int ny, int nz, int channe
         if (!(spacing_A > 0.0) || !isfinite(spacing_A)) return fail(EXS_EINVAL, "spacing must be > 0");
         if (storage != EXS_F32 && storage != EXS_BF16 && storage != EXS_F16)
             return fail(EXS_EINVAL, "unknown storage %d", storage);
+        if ((int64_t)nx * ny >= (int64_t)1 << 23 || nz >= 1 << 23)
+            return fail(EXS_EINVAL, "grid %dx%dx%d: nx*ny and nz must be below 2^23 (cell offsets use 24-bit multiplies)",
+                        nx, ny, nz);
         const int64_t chan = (int64_t)nx * ny * nz;
         const int64_t tex_chan_bytes = expanded_entries(nx, ny, nz, storage) * 16;
         if (tex_chan_bytes > INT32_MAX)

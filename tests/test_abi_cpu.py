@@ -139,3 +139,23 @@ def test_texels_that_overflow_16bit_storage_are_refused(B, storage, bad, good):
         B.exs_unload_pocket(pid)
     except B.ExsError as e:            # no GPU here: validation passed, the device call failed
         assert e.code != B.EXS_EINVAL, str(e)
+
+
+@pytest.mark.parametrize("nx,ny,nz,ok", [
+    (4096, 2048, 2, False),           # nx * ny = 2^23
+    (2, 2, 1 << 23, False),           # nz = 2^23
+    (2896, 2896, 2, True),            # nx * ny just below 2^23
+])
+def test_grid_dimensions_beyond_24_bit_offsets_are_refused(B, nx, ny, nz, ok):
+    """The search forms cell offsets with 24-bit multiplies, so a grid whose x-y slice or z edge
+    reaches 2^23 texels is refused with EXS_EINVAL before any device work; one just below
+    passes validation (here, with no GPU, it then fails on the device call instead)."""
+    vals = np.zeros((1, nz, ny, nx), np.float32)
+    try:
+        pid = B.exs_load_pocket_grid(vals, 0.5, np.zeros(3), B.EXS_F32)
+        B.exs_unload_pocket(pid)
+        assert ok
+    except B.ExsError as e:
+        assert (e.code == B.EXS_EINVAL) == (not ok), str(e)
+        if not ok:
+            assert "2^23" in str(e)
