@@ -321,16 +321,9 @@ def test_16bit_texels_match_oracle_on_rounded_grid(B, oracle_lib, small, storage
     log("16-bit stats", stats)
 
 
-def test_fp64_rescoring_of_top_k(B, oracle_lib, small):
-    """top_k poses per ligand rescored in FP64 on the GPU equal the oracle's FP64 score of the
-    same descriptors; the final best is the FP64 argmin among them."""
-    O = oracle_lib
-    p, g, batch = small
-    s = S.SMALL.search
-    sub = batch.subset(range(12))
-    tk = 8
-    log("fp64 rescoring top_k=%d" % tk)
-    out = run(B, [p], sub, s, top_k=tk)
+def check_topk(O, g, s, sub, out, tk):
+    """top_k descriptors are the K best FP32 poses, each FP64 score equals the oracle's FP64
+    score of the same descriptor, and the final best is their FP64 argmin."""
     prm = O.Params.of(s)
     for l in range(sub.n_ligands):
         lig = sub.ligand(l)
@@ -353,6 +346,37 @@ def test_fp64_rescoring_of_top_k(B, oracle_lib, small):
         X = O.pose_from_desc(g, prm, lig, int(top[j]["orient"]), top[j]["theta"][:len(lig.rot)],
                              top[j]["tau"])
         assert np.max(np.abs(out["coords"][a0:a1] - X)) < 1e-5
+
+
+def test_fp64_rescoring_of_top_k(B, oracle_lib, small):
+    """top_k poses per ligand rescored in FP64 on the GPU equal the oracle's FP64 score of the
+    same descriptors; the final best is the FP64 argmin among them."""
+    O = oracle_lib
+    p, g, batch = small
+    s = S.SMALL.search
+    sub = batch.subset(range(12))
+    tk = 8
+    log("fp64 rescoring top_k=%d" % tk)
+    out = run(B, [p], sub, s, top_k=tk)
+    check_topk(O, g, s, sub, out, tk)
+
+
+def test_fp64_rescoring_of_top_k_on_the_largest_ligands(B, oracle_lib, small):
+    """The FP64 rescoring with two atoms per lane: ligands of 64, 65, 101 and 128 atoms (even
+    and odd counts, so that every rule of the pair split over the atoms is taken) and up to 32
+    rotatable bonds; the clash counts, scores and choice equal the oracle's as above."""
+    O = oracle_lib
+    p, g, _ = small
+    ligs = []
+    for i, (n, nrot) in enumerate(((64, 6), (65, 9), (101, 20), (128, 32))):
+        wl = S.Workload("big%d" % n, 96 + i, 1, 1, (48,), 0.5, 4, ("fixed", n), ("fixed", nrot),
+                        S.SMALL.search)
+        ligs += S.make_ligands(wl, 0, 1)
+    sub = S.batch_from_ligands(ligs)
+    tk = 8
+    log("fp64 rescoring top_k=%d, n=%s" % (tk, [l.n for l in ligs]))
+    out = run(B, [p], sub, S.SMALL.search, top_k=tk)
+    check_topk(O, g, S.SMALL.search, sub, out, tk)
 
 
 def test_graph_replays_match_eager(B, small):

@@ -90,6 +90,25 @@ def test_rescored_poses_match_oracle(B, oracle_lib):
     assert decided >= batch.n_ligands // 2
 
 
+def test_rescoring_of_the_largest_ligands(B, oracle_lib):
+    """Two atoms per lane: ligands of 64, 65, 101 and 128 atoms (even and odd counts, so that
+    every rule of the pair split over the atoms is taken) and up to 32 rotatable bonds; every
+    ranked pose's second-stage score matches the oracle's."""
+    O = oracle_lib
+    p = S.make_pocket("small")
+    ligs = []
+    for i, (n, nrot) in enumerate(((64, 6), (65, 9), (101, 20), (128, 32))):
+        wl = S.Workload("big%d" % n, 100 + i, 1, 1, (48,), 0.5, 4, ("fixed", n), ("fixed", nrot),
+                        S.SearchSettings(64, 8, 1, 27))
+        ligs += S.make_ligands(wl, 0, 1)
+    batch = S.batch_from_ligands(ligs)
+    s = S.SearchSettings(64, 8, 1, 27)
+    log("second-stage rescoring of n=%s" % [l.n for l in ligs])
+    r2, ranked, orient = run(B, [p], batch, s)
+    worst, decided = check(O, [O.Grid.of(p)], s, batch, r2, ranked, orient)
+    log("max relative error %.3g, oracle choice clear-cut on %d ligands" % (worst, decided))
+
+
 def test_rescoring_persistent_graph_equals_per_pocket(B, oracle_lib):
     """Uneven ligands over two pockets, up to 15 rotatable bonds: one persistent launch replayed
     from a hipGraph equals the per-pocket launches bit for bit, and a sample matches the oracle."""
