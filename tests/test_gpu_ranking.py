@@ -127,6 +127,24 @@ def test_ranking_with_offsets_and_persistent_launch(B, oracle_lib):
     log("ranking (T=27, K=100) stats", stats)
 
 
+def test_ranking_of_the_largest_ligands(B, oracle_lib):
+    """Ligands of 64, 65, 101 and 128 atoms (pose rows in whole batches of 8 and with a tail)
+    and up to 32 rotatable bonds: the ranking matches the oracle."""
+    O = oracle_lib
+    pocket = S.make_pocket("small")
+    ligs = []
+    for i, (n, nrot) in enumerate(((64, 6), (65, 9), (101, 20), (128, 32))):
+        wl = S.Workload("big%d" % n, 96 + i, 1, 1, (48,), 0.5, 4, ("fixed", n), ("fixed", nrot),
+                        S.SMALL.search)
+        ligs += S.make_ligands(wl, 0, 1)
+    batch = S.batch_from_ligands(ligs)
+    s = S.SMALL.search
+    nc, rk, orient = run_ranked(B, pocket, batch, s, 3.0, s.n_orient)
+    stats = {}
+    check_ranking(O, O.Grid.of(pocket), O.Params.of(s), batch, nc, rk, orient, 3.0, s.n_orient, stats)
+    log("ranking (n = 64-128) stats", stats)
+
+
 def test_ranking_request_errors(B):
     pocket = S.make_pocket("small")
     batch = S.make_ligand_batch("small").subset(range(2))
