@@ -721,6 +721,39 @@ def batched_launch(B, torch, pids, batch, s, storage, top_k, steps, warmup, stre
     return batch.n_ligands * steps / dt, kms, dt / steps, out
 
 
+def method_work(binding, batch, search, channels, clusters, keep, unfold_passes):
+    """Algorithmic lane-ops of the method's other steps, summed over the ligands (FP32 for the
+    unfolding and the ranking, FP64 for the second-stage rescoring; both run at one lane-op per
+    lane and cycle on the vector ALU):
+      unfolding  passes * sum_b S * m_b * (9 (n - m_b) + 12)
+                 (S turn positions of each moving atom, 12 lane-ops each, and its distance to
+                 every static atom, 9: three differences, three products, root, sum);
+      ranking    K^2 (rank of each pose by score) + 2 * K * c * 3n
+                 (each pose against each of the c leaders: a difference and an fma per row);
+      rescoring  keep * (30 n + 12 c0 + 40 B + 20 (n + sum_b m_b))
+                 (per pose: n FP64 trilinear lookups, c0 contact pairs, B torsion terms and the
+                 FP64 rebuild).
+    m_b = atoms turning with bond b, c0 = non-excluded pairs, c = the ligand's clusters."""
+    S_, K = search.torsion_steps, search.n_orient
+    unf = rank = res = 0.0
+    for l in range(batch.n_ligands):
+        lig = batch.ligand(l)
+        t = binding.exs_pack_topology(lig, channels)
+        n = lig.n
+        c0 = (n * n - int(t["excl"].sum())) // 2
+        ms = [int(t["moving"][b].sum()) for b in range(len(lig.rot))]
+        unf += unfold_passes * sum(S_ * m * (9 * (n - m) + 12) for m in ms)
+        rank += K * K + 2.0 * K * float(clusters[l]) * 3 * n
+        res += keep * (30 * n + 12 * c0 + 40 * len(ms) + 20 * (n + sum(ms)))
+    return {"unfold": unf, "rank": rank, "rescore2": res}
+
+
+def step_roofline(ops, ms):
+    tops = ops / (ms * 1e-3) / 1e12
+    return {"ms": round(ms, 3), "bound": "alu", "lane_ops": float(ops), "achieved": round(tops, 3),
+            "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4)}
+
+
 def method_steps_leg(B, torch, S, pid, s, stream, n=3000):
     """The method's other steps on the first `n` scale ligands (Sec. 3.1): unfolding of the
     input conformations (S = 32, 2 passes; host wall time of the call), then one dock job as
@@ -731,35 +764,47 @@ def method_steps_leg(B, torch, S, pid, s, stream, n=3000):
     bid = B.exs_upload_ligands(batch, pocket_ids=[pid], stream=stream)
     try:
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(stream)
         B.exs_unfold_ligands(bid, s.torsion_steps, 2, stream=stream)
+        e1.record(stream)
         unfold_ms = (time.perf_counter() - t0) * 1e3
+        e1.synchronize()
+        unfold_kernel_ms = e0.elapsed_time(e1)   # the kernel, bracketed on its own stream
 
         def job_ms(prm, ranked):
-            ms, nc = [], None
+            ms, nc, stages = [], None, []
             for _ in range(4):
                 job = B.exs_dock_batch(bid, prm, stream=stream)
                 B.exs_get_best_poses(job, L, A)
                 if ranked:
                     nc, _ = B.exs_get_ranked_poses(job, L, 30)
                     B.exs_get_rescored_poses(job, L, 30)
+                    stages.append(B.exs_job_stage_ms(job))
                 ms.append(B.exs_job_elapsed_ms(job))
                 B.exs_release_job(job)
-            return float(np.median(ms[1:])), nc
+            med = {k: float(np.median([st[k] for st in stages[1:]])) for k in ("rank", "rescore2")} \
+                if ranked else None
+            return float(np.median(ms[1:])), nc, med
 
         plain = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                                 s.clash_cutoff, s.clash_penalty)
         ranked = B.search_params(s.n_orient, s.torsion_steps, s.passes, s.n_offsets, s.offset_step,
                                  s.clash_cutoff, s.clash_penalty, flags=B.EXS_FLAG_RESCORE2,
                                  cluster_rmsd_A=3.0, rank_keep=30)
-        dock_ms, _ = job_ms(plain, False)
-        full_ms, nc = job_ms(ranked, True)
+        dock_ms, _, _ = job_ms(plain, False)
+        full_ms, nc, st_ms = job_ms(ranked, True)
     finally:
         B.exs_release_ligands(bid)
+    work = method_work(B, batch, s, S.WORKLOADS["scale"].channels, nc, 30, 2)
     return {"ligands": L, "unfold_ms": round(unfold_ms, 3), "dock_ms": round(dock_ms, 3),
             "dock_rank_rescore2_ms": round(full_ms, 3),
             "rank_rescore2_ms": round(full_ms - dock_ms, 3),
             "clusters_mean": round(float(nc.mean()), 2),
+            "roofline": {"unfold": step_roofline(work["unfold"], unfold_kernel_ms),
+                         "rank": step_roofline(work["rank"], st_ms["rank"]),
+                         "rescore2": step_roofline(work["rescore2"], st_ms["rescore2"])},
             "steps": "unfold (S=32, 2 passes), dock, rank (3 A, keep 30), second-stage rescoring"}
 
 

@@ -346,6 +346,16 @@ int exs_dock_batch_noalloc(int64_t batch, const exs_search_params* params, void*
 /* Device time of the job's kernels in ms (waits for the job). */
 int exs_job_elapsed_ms(int64_t job, float* ms);
 
+/*
+ * Device time of each step of the job in ms (waits for the job), from events recorded between
+ * its kernels on the job's stream: the search (Sec. 3.1, second step), the ranking of the final
+ * poses (third step) and the second-stage rescoring (fourth step).  A step the job did not run
+ * reads -1.  A job launched from a graph (EXS_FLAG_GRAPH) or without ranking is not staged:
+ * dock_ms is then the whole job, as exs_job_elapsed_ms gives it.
+ * Errors: EXS_ENOENT (unknown job), EXS_EINVAL (null output), EXS_EDEVICE.
+ */
+int exs_job_stage_ms(int64_t job, float* dock_ms, float* rank_ms, float* rescore2_ms);
+
 /* Free a job's device results. */
 int exs_release_job(int64_t job);
 

@@ -30,7 +30,7 @@ STORAGE = {"f32": EXS_F32, "bf16": EXS_BF16, "f16": EXS_F16}
 SYMBOLS = ("exs_version", "exs_last_error", "exs_load_pocket_grid", "exs_unload_pocket",
            "exs_upload_ligands", "exs_release_ligands", "exs_pack_topology", "exs_dock_batch", "exs_get_best_poses",
            "exs_get_orientation_results", "exs_get_ranked_poses", "exs_unfold_ligands",
-           "exs_get_ligand_coords", "exs_job_elapsed_ms",
+           "exs_get_ligand_coords", "exs_job_elapsed_ms", "exs_job_stage_ms",
            "exs_release_job", "exs_gather_probe",
            "exs_server_create", "exs_server_submit", "exs_server_poll", "exs_server_get_stats",
            "exs_server_destroy", "exs_dock_batch_noalloc", "exs_get_rescored_poses",
@@ -117,6 +117,8 @@ def lib():
                                              vp, vp]
         L.exs_get_orientation_results.argtypes = [i64, vp, vp]
         L.exs_job_elapsed_ms.argtypes = [i64, C.POINTER(C.c_float)]
+        L.exs_job_stage_ms.argtypes = [i64, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                       C.POINTER(C.c_float)]
         L.exs_release_job.argtypes = [i64]
         L.exs_get_ranked_poses.argtypes = [i64, C.c_int, vp, vp]
         L.exs_get_rescored_poses.argtypes = [i64, C.c_int, vp, vp, vp]
@@ -322,6 +324,14 @@ def exs_job_elapsed_ms(job: int) -> float:
     ms = C.c_float()
     _check(lib().exs_job_elapsed_ms(int(job), C.byref(ms)))
     return float(ms.value)
+
+
+def exs_job_stage_ms(job: int) -> dict:
+    """Device ms of the search, the ranking and the second-stage rescoring of an eager ranked
+    job (-1 for a step not run; an unstaged job gives its whole time as "dock")."""
+    d, r, q = C.c_float(), C.c_float(), C.c_float()
+    _check(lib().exs_job_stage_ms(int(job), C.byref(d), C.byref(r), C.byref(q)))
+    return {"dock": float(d.value), "rank": float(r.value), "rescore2": float(q.value)}
 
 
 def exs_release_job(job: int):

@@ -166,6 +166,7 @@ struct Job {
     exs_search_params prm{};
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_dock = nullptr, ev_rank = nullptr;   // eager ranked jobs: after the search, after the ranking
     int L = 0, A = 0, R = 0, K = 0, top_k = 0;
     std::vector<void*> bufs;    // stream-ordered allocations (eager jobs)
     std::shared_ptr<Plan> plan; // graph jobs: buffers belong to the plan
@@ -725,7 +726,9 @@ void job_free(Job& j) {
     if (j.plan) { j.plan->busy = false; j.plan.reset(); }
     if (j.ev0) (void)hipEventDestroy(j.ev0);
     if (j.ev1) (void)hipEventDestroy(j.ev1);
-    j.ev0 = j.ev1 = nullptr;
+    if (j.ev_dock) (void)hipEventDestroy(j.ev_dock);
+    if (j.ev_rank) (void)hipEventDestroy(j.ev_rank);
+    j.ev0 = j.ev1 = j.ev_dock = j.ev_rank = nullptr;
 }
 
 }  // namespace
@@ -769,9 +772,12 @@ namespace {
 
 // The launch sequence of one job on `st`: a counter reset and one persistent dock
 // launch, or one dock launch per pocket group.
+// ev_dock / ev_rank (may be null): recorded on `st` after the search and after the ranking, so
+// that an eager job can report each kernel's time (never inside a graph capture).
 hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<int>& groups,
                         const int32_t* d_order, int n_queues, int storage, int ppl, bool persistent,
-                        int resident, int threads, size_t lds, hipStream_t st) {
+                        int resident, int threads, size_t lds, hipStream_t st,
+                        hipEvent_t ev_dock = nullptr, hipEvent_t ev_rank = nullptr) {
     if (b.L == 0) return hipSuccess;
     if (persistent) {
         DockArgs a = base;
@@ -784,7 +790,9 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         hipError_t e = launch_zero_ints(a.tile_counter, n_queues, st);
         if (e != hipSuccess) return e;
         e = launch_dock(a, storage, ppl, resident, threads, lds, st);
+        if (e == hipSuccess && ev_dock) e = hipEventRecord(ev_dock, st);
         if (e == hipSuccess && a.rank_keep > 0) e = launch_rank(a, b.L, d_order, st);
+        if (e == hipSuccess && ev_rank) e = hipEventRecord(ev_rank, st);
         if (e == hipSuccess && a.rescore2) e = launch_rescore2(a, b.L, d_order, st);
         return e;
     }
@@ -801,9 +809,10 @@ hipError_t enqueue_dock(const DockArgs& base, const Batch& b, const std::vector<
         if (e != hipSuccess) return e;
         start += gsz;
     }
-    hipError_t e = hipSuccess;
+    hipError_t e = ev_dock ? hipEventRecord(ev_dock, st) : hipSuccess;
     // d_order: every pocket's ligands, longest first, one pocket after another
-    if (base.rank_keep > 0) e = launch_rank(base, b.L, d_order, st);
+    if (e == hipSuccess && base.rank_keep > 0) e = launch_rank(base, b.L, d_order, st);
+    if (e == hipSuccess && ev_rank) e = hipEventRecord(ev_rank, st);
     if (e == hipSuccess && base.rescore2) e = launch_rescore2(base, b.L, d_order, st);
     return e;
 }
@@ -1031,12 +1040,16 @@ int exs_dock_batch(int64_t batch, const exs_search_params* params, void* stream,
         }
         HIP_TRY(hipEventCreate(&j->ev0));
         HIP_TRY(hipEventCreate(&j->ev1));
+        if (!j->plan && p.rank_keep > 0 && b->L > 0) {
+            HIP_TRY(hipEventCreate(&j->ev_dock));
+            HIP_TRY(hipEventCreate(&j->ev_rank));
+        }
         HIP_TRY(hipEventRecord(j->ev0, st));
         if (j->plan) {
             HIP_TRY(hipGraphLaunch(j->plan->exec, st));
         } else {
             HIP_TRY(enqueue_dock(j->args, *b, groups, d_order, n_queues, storage, ppl, persistent,
-                                 resident, threads, lds, st));
+                                 resident, threads, lds, st, j->ev_dock, j->ev_rank));
         }
         HIP_TRY(hipEventRecord(j->ev1, st));
         std::lock_guard<std::mutex> lk(g_reg_mu);
@@ -1179,6 +1192,26 @@ int exs_job_elapsed_ms(int64_t job, float* ms) {
     if (!ms) return fail(EXS_EINVAL, "null argument");
     if (int rc = job_wait(*j, 1)) return rc;
     HIP_TRY(hipEventElapsedTime(ms, j->ev0, j->ev1));
+    return EXS_OK;
+}
+
+int exs_job_stage_ms(int64_t job, float* dock_ms, float* rank_ms, float* rescore2_ms) {
+    auto j = find_job(job);
+    if (!j) return fail(EXS_ENOENT, "unknown job %lld", (long long)job);
+    if (!dock_ms || !rank_ms || !rescore2_ms) return fail(EXS_EINVAL, "null argument");
+    if (int rc = job_wait(*j, 1)) return rc;
+    *rank_ms = *rescore2_ms = -1.0f;
+    if (!j->ev_dock) {   // not staged: the whole job
+        HIP_TRY(hipEventElapsedTime(dock_ms, j->ev0, j->ev1));
+        return EXS_OK;
+    }
+    HIP_TRY(hipEventElapsedTime(dock_ms, j->ev0, j->ev_dock));
+    if (j->args.rescore2) {
+        HIP_TRY(hipEventElapsedTime(rank_ms, j->ev_dock, j->ev_rank));
+        HIP_TRY(hipEventElapsedTime(rescore2_ms, j->ev_rank, j->ev1));
+    } else {   // the ranking ends the job
+        HIP_TRY(hipEventElapsedTime(rank_ms, j->ev_dock, j->ev1));
+    }
     return EXS_OK;
 }
 

@@ -69,3 +69,16 @@ def test_roofline_bound_is_the_larger_fraction(bench, B):
     alu = roof if roof["bound"] == "alu" else roof["other"]
     assert alu["frac_if_every_turn_tested"] == pytest.approx(
         64 * (30 * 293 + 7 * (1 + 7 * 2) + 15 * 28) / 1e-6 / 1e12 / bench.VALU_PEAK_TOPS, abs=1e-4)
+
+
+def test_method_step_counts_of_a_five_atom_chain(bench, B):
+    """Chain 0-1-2-3-4, rotatable bond 1-2 (moving side {3, 4}, m = 2), S=8, K=64, 2 unfolding
+    passes, 3 clusters, 30 ranked poses kept.  Unfolding: 2 x 8 x 2 x (9 x 3 + 12) = 1,248.
+    Ranking: 64^2 + 2 x 64 x 3 x 15 = 9,856.  Rescoring: c0 = 1 pair (0, 4), one bond, so
+    30 x (30 x 5 + 12 x 1 + 40 x 1 + 20 x (5 + 2)) = 30 x 342 = 10,260."""
+    batch = S.batch_from_ligands([chain(5, [1])])
+    search = S.SearchSettings(64, 8, 2, 27)
+    w = bench.method_work(B, batch, search, 4, np.array([3]), 30, 2)
+    assert w == {"unfold": 1248, "rank": 9856, "rescore2": 10260}
+    r = bench.step_roofline(w["rank"], 1e-3)   # 9,856 lane-ops in 1 microsecond
+    assert r["bound"] == "alu" and r["frac"] == pytest.approx(9856 / 1e-6 / 1e12 / bench.VALU_PEAK_TOPS, abs=1e-4)

@@ -146,3 +146,37 @@ def test_rescoring_request_errors(B):
         B.exs_release_ligands(bid)
     finally:
         B.exs_unload_pocket(pid)
+
+
+def test_job_stage_times(B):
+    """exs_job_stage_ms: an eager job that ranks and rescores reports the time of each step,
+    positive and adding up to the job's time; a job that ranks without rescoring reads -1 for
+    the rescoring, and a job without ranking gives its whole time as the search."""
+    p = S.make_pocket("small")
+    batch = S.make_ligand_batch("small", 0, 16)
+    pid = B.exs_load_pocket_grid(p.values, p.spacing, p.origin)
+    bid = None
+    try:
+        bid = B.exs_upload_ligands(batch, pocket_ids=[pid])
+        for flags, keep in ((B.EXS_FLAG_RESCORE2, KEEP), (0, KEEP), (0, 0)):
+            prm = B.search_params(64, 16, 1, 27, flags=flags, cluster_rmsd_A=3.0, rank_keep=keep)
+            job = B.exs_dock_batch(bid, prm)
+            st = B.exs_job_stage_ms(job)
+            tot = B.exs_job_elapsed_ms(job)
+            B.exs_release_job(job)
+            log("stages", flags, keep, st, tot)
+            assert st["dock"] > 0
+            if keep:
+                assert st["rank"] > 0
+            else:
+                assert st["rank"] == -1 and st["rescore2"] == -1
+            if flags:
+                assert st["rescore2"] > 0
+            elif keep:
+                assert st["rescore2"] == -1
+            parts = st["dock"] + max(st["rank"], 0.0) + max(st["rescore2"], 0.0)
+            assert abs(parts - tot) <= 1e-3 + 1e-3 * tot, (parts, tot)
+    finally:
+        if bid is not None:
+            B.exs_release_ligands(bid)
+        B.exs_unload_pocket(pid)
