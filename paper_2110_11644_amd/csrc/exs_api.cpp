@@ -446,6 +446,7 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
         // validate, pack and flatten on host threads, each ligand into its own ranges
         std::vector<int> rc_of(L, EXS_OK);
         std::vector<std::string> err_of(L);
+        std::vector<double> cost(L, 0.0);   // search cost at the full settings (the upload order)
         unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         if (L < 256) nth = 1;
         std::atomic<int> next{0};
@@ -497,6 +498,7 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
                     rmask[r0 + r] = p.moving[r].as_uint4();
                     b->mcount[l][r] = (int16_t)p.moving[r].count();
                 }
+                cost[l] = ligand_cost(p.n, b->mcount[l].data(), p.nrot, 1, 32, 2, 27);
                 } catch (const std::exception& ex) {
                     rc_of[l] = EXS_ENOMEM;
                     err_of[l] = std::string("exception: ") + ex.what();
@@ -524,12 +526,8 @@ int exs_upload_ligands(const exs_ligand_batch* in, void* stream, int64_t* batch_
         // full search settings (the order of launches that cannot build one of their own)
         int32_t* up_order = reinterpret_cast<int32_t*>(hb + o_order);
         {
-            std::vector<double> cost(L);
             std::vector<int> pocket(L);
-            for (int l = 0; l < L; ++l) {
-                cost[l] = ligand_cost(b->info[l].n, b->mcount[l].data(), b->info[l].nrot, 1, 32, 2, 27);
-                pocket[l] = b->info[l].pocket;
-            }
+            for (int l = 0; l < L; ++l) pocket[l] = b->info[l].pocket;
             work_queues(L, pocket.data(), cost.data(), 1, true, up_order, up_order + L);
         }
         hipStream_t st = (hipStream_t)stream;
