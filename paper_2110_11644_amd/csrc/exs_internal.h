@@ -192,9 +192,9 @@ struct DockArgs {
 
 // LDS words per wave of the ranking kernel: rank, state and score per pose, the leader bits,
 // the coordinates of 8 candidate leaders (3 n_max rows each, n_max the launch's largest
-// ligand), their mutual distances and the list of uncovered poses.
+// ligand) and the list of uncovered poses.
 __host__ __device__ inline int rank_lds_words(int K, int n_max) {
-    return 4 * K + (K + 31) / 32 + 8 * 3 * n_max + 8 * 8;
+    return 4 * K + (K + 31) / 32 + 8 * 3 * n_max;
 }
 
 // Per-ligand LDS staging of a tile (topology read wave-uniformly by the search).
